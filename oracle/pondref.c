@@ -266,6 +266,7 @@ static void matvec(int Q, const double* G, const double* in, double* out) {
 /* State.                                                                    */
 /* ------------------------------------------------------------------------ */
 #define NG 2 /* ghost layers */
+#define TIE_BAND 1e-11 /* |v_n| <= TIE_BAND sqrt(T_F) is an upwind tie */
 #define QMAX 16
 
 struct pondref_state {
@@ -660,9 +661,12 @@ static void face_flux(const pondref_state* s, const face_stencil* st, double* fo
         const double recR = reconstruct(s->cfg.limiter, P[1][i], P[0][i], P[3][i],
                                         twod ? P[7][i] : 0.0, twod ? P[6][i] : 0.0,
                                         -0.5 - 0.5 * lam * vn, dtv, twod);
-        /* upwind by the sign of the normal velocity; reading: an exact tie
-           takes the mean of both reconstructions */
-        out[i] = vn > 0.0 ? recL : (vn < 0.0 ? recR : 0.5 * (recL + recR));
+        /* upwind by the sign of the normal velocity.  reading: a normal
+           velocity within TIE_BAND of the face thermal speed counts as zero
+           (rounding noise around a fluid at rest must not pick a side), and
+           a tie takes the mean of both reconstructions */
+        const double band = TIE_BAND * rt;
+        out[i] = vn > band ? recL : (vn < -band ? recR : 0.5 * (recL + recR));
       }
     }
     /* macroscopic fields at the face from f-bar and g-bar in lambda_F */

@@ -1,0 +1,480 @@
+// Host side of libpond.so: configuration checks, arena layout, the initial
+// state, the step loop and the observables.  Every computation on the state
+// runs in the kernels of pond_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pond.h"
+#include "pond_internal.h"
+#include "pond_state.h"
+
+namespace pond {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(POND_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define POND_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int validate(const pond_config* c) {
+  if (!c) return fail(POND_ERR_INVALID, "null config");
+  if (c->dim != 1 && c->dim != 2) return fail(POND_ERR_INVALID, "dim must be 1 or 2");
+  if (c->nx < 1 || c->ny < 1 || (c->dim == 1 && c->ny != 1))
+    return fail(POND_ERR_INVALID, "grid needs nx >= 1, ny >= 1 (ny = 1 in 1D)");
+  if ((c->dim == 1 && c->lattice != POND_D1Q4) || (c->dim == 2 && c->lattice != POND_D2Q16))
+    return fail(POND_ERR_INVALID, "lattice must be D1Q4 in 1D and D2Q16 in 2D");
+  if (c->precision != POND_FP64 && c->precision != POND_MIXED)
+    return fail(POND_ERR_INVALID, "unknown precision");
+  if (c->transform != POND_TF_LAGRANGE && c->transform != POND_TF_GRAD)
+    return fail(POND_ERR_INVALID, "unknown transform");
+  if (!(c->gamma > 1.0)) return fail(POND_ERR_INVALID, "gamma must exceed 1");
+  if (!(c->tau > 0.0)) return fail(POND_ERR_INVALID, "tau must be positive");
+  if (!(c->prandtl > 0.0 && c->prandtl <= 1.0)) return fail(POND_ERR_INVALID, "Pr must lie in (0, 1]");
+  if (!(c->cfl > 0.0)) return fail(POND_ERR_INVALID, "cfl must be positive");
+  if (!(c->dx >= 0.0) || !std::isfinite(c->dx)) return fail(POND_ERR_INVALID, "dx must be >= 0");
+  if (c->limiter != POND_LIM_VANLEER && c->limiter != POND_LIM_MINMOD)
+    return fail(POND_ERR_INVALID, "unknown limiter");
+  if (c->n_corr < 0 || c->n_corr > 4) return fail(POND_ERR_INVALID, "n_corr must lie in 0..4");
+  const int nside = c->dim == 2 ? 4 : 2;
+  for (int k = 0; k < nside; ++k)
+    if (c->bc[k] < POND_BC_PERIODIC || c->bc[k] > POND_BC_INFLOW)
+      return fail(POND_ERR_INVALID, "unknown boundary condition");
+  for (int k = 0; k < nside; k += 2)
+    if ((c->bc[k] == POND_BC_PERIODIC) != (c->bc[k + 1] == POND_BC_PERIODIC))
+      return fail(POND_ERR_INVALID, "a periodic axis needs periodic conditions on both sides");
+  for (int k = 0; k < nside; ++k)
+    if (c->bc[k] == POND_BC_INFLOW) {
+      const double* s = c->inflow[k];
+      if (!(s[0] > 0.0) || !(s[3] > 0.0) || !std::isfinite(s[1]) || !std::isfinite(s[2]))
+        return fail(POND_ERR_INVALID, "inflow state needs positive density and pressure");
+    }
+  if (c->transform == POND_TF_GRAD)
+    return fail(POND_ERR_UNSUPPORTED, "the GPU step implements the Lagrange transform only");
+  return POND_OK;
+}
+
+Layout layout_of(const pond_config* c) {
+  Layout L;
+  L.D = c->dim;
+  L.QF = c->dim == 2 ? 16 : 4;
+  L.QG = c->dim == 2 ? 9 : 3;
+  L.NP = L.QF + L.QG;
+  L.fp64 = c->precision == POND_FP64;
+  L.cells = size_t(c->nx) * size_t(c->ny);
+  const size_t elt = L.fp64 ? 8 : 4;
+  L.pop_bytes = align256(size_t(L.NP) * L.cells * elt);
+  L.led_bytes = align256(4 * L.cells * sizeof(long long));
+  L.red_blocks = 256;
+  L.red_bytes = align256(size_t(L.red_blocks) * 8 * sizeof(long long));
+  L.stage_rows = size_t(std::max(4, L.NP + 3));
+  L.stage_cells = std::min(L.cells, size_t(kStagingBytes / (8 * L.stage_rows)));
+  L.stage_bytes = align256(L.stage_rows * L.stage_cells * 8);
+  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 256 + L.red_bytes + L.stage_bytes;
+  return L;
+}
+
+static int check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(POND_ERR_DEVICE, std::string("libpond needs a gfx950 device, found ") + prop.gcnArchName);
+  return POND_OK;
+}
+
+// Fixed-point exponent E of the ledger: the largest |conserved moment| M of
+// the initial data must satisfy M 2^E <= 2^56, leaving a factor 64 of
+// headroom below the 2^62 overflow guard.
+static int ledger_bits(double M) {
+  int e = 0;
+  std::frexp(std::max(M, 1e-300), &e);  // M < 2^e
+  return 56 - e;
+}
+
+static void conserved_of(double rho, double ux, double uy, double p, double cv, double out[4]) {
+  out[0] = rho;
+  out[1] = rho * ux;
+  out[2] = rho * uy;
+  out[3] = cv * p + 0.5 * rho * (ux * ux + uy * uy);
+}
+
+static int sync_flag(pond_state* s) {
+  POND_HIP(hipStreamSynchronize(s->stream));
+  int flag = 0;
+  POND_HIP(hipMemcpy(&flag, s->flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag & 2) return fail(POND_ERR_UNSTABLE, "conserved-moment ledger overflow");
+  if (flag & 1) return fail(POND_ERR_UNSTABLE, "non-physical state (rho <= 0, T <= 0 or non-finite)");
+  return POND_OK;
+}
+
+}  // namespace pond
+
+using namespace pond;
+
+extern "C" {
+
+int pond_last_error(char* buf, size_t n) {
+  if (buf && n) {
+    std::strncpy(buf, g_last_error.c_str(), n - 1);
+    buf[n - 1] = 0;
+  }
+  return POND_OK;
+}
+
+size_t pond_state_bytes(const pond_config* cfg) {
+  if (validate(cfg) != POND_OK) return 0;
+  return layout_of(cfg).total;
+}
+
+int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                pond_state** out) {
+  if (!out) return fail(POND_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if ((rc = check_device())) return rc;
+  const Layout L = layout_of(cfg);
+  if (!dev_arena || (reinterpret_cast<uintptr_t>(dev_arena) & 255))
+    return fail(POND_ERR_INVALID, "arena must be a 256-byte aligned device pointer");
+  if (arena_bytes < L.total)
+    return fail(POND_ERR_NOMEM, "arena of " + std::to_string(arena_bytes) + " bytes, need " +
+                                    std::to_string(L.total));
+  pond_state* s = new pond_state();
+  s->cfg = *cfg;
+  s->L = L;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  char* p = static_cast<char*>(dev_arena);
+  s->n[0] = p; p += L.pop_bytes;
+  s->n[1] = p; p += L.pop_bytes;
+  s->U[0] = reinterpret_cast<long long*>(p); p += L.led_bytes;
+  s->U[1] = reinterpret_cast<long long*>(p); p += L.led_bytes;
+  s->flag = reinterpret_cast<int*>(p); p += 256;
+  s->red = reinterpret_cast<long long*>(p); p += L.red_bytes;
+  s->stage = reinterpret_cast<double*>(p);
+  s->dx = cfg->dx > 0.0 ? cfg->dx : 1.0 / cfg->nx;
+  s->cv = 1.0 / (cfg->gamma - 1.0);
+  hipError_t e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipMemsetAsync");
+  }
+  *out = s;
+  return POND_OK;
+}
+
+int pond_init_fields(pond_state* s, const double* rho, const double* ux, const double* uy,
+                     const double* p) {
+  if (!s || !rho || !ux || !p) return fail(POND_ERR_INVALID, "null argument");
+  const pond_config& c = s->cfg;
+  const size_t n = s->L.cells;
+  const bool twod = c.dim == 2;
+  if (twod && !uy) return fail(POND_ERR_INVALID, "uy is required in 2D");
+  // dt from the CFL rule at t = 0 (Sec. V): max over cells, nodes and axes
+  // of |sqrt(T) c_ia + u_a|
+  double vmax = 0.0, M = 0.0, U4[4];
+  for (size_t k = 0; k < n; ++k) {
+    const double vy = twod ? uy[k] : 0.0;
+    if (!(rho[k] > 0.0) || !(p[k] > 0.0) || !std::isfinite(rho[k]) || !std::isfinite(p[k]) ||
+        !std::isfinite(ux[k]) || !std::isfinite(vy))
+      return fail(POND_ERR_INVALID, "initial density and pressure must be positive and finite");
+    const double rt = std::sqrt(p[k] / rho[k]);
+    vmax = std::max(vmax, std::fabs(ux[k]) + rt * kB);
+    if (twod) vmax = std::max(vmax, std::fabs(vy) + rt * kB);
+    conserved_of(rho[k], ux[k], vy, p[k], s->cv, U4);
+    for (double v : U4) M = std::max(M, std::fabs(v));
+  }
+  const int nside = twod ? 4 : 2;
+  for (int k = 0; k < nside; ++k)
+    if (c.bc[k] == POND_BC_INFLOW) {
+      const double* st = c.inflow[k];
+      conserved_of(st[0], st[1], twod ? st[2] : 0.0, st[3], s->cv, U4);
+      for (double v : U4) M = std::max(M, std::fabs(v));
+    }
+  s->dt = c.cfl * s->dx / vmax;
+  s->scale_bits = ledger_bits(M);
+  s->scale = std::ldexp(1.0, s->scale_bits);
+  for (int k = 0; k < 4; ++k) {
+    const double* st = c.inflow[k];
+    if (c.bc[k] != POND_BC_INFLOW) {
+      for (int q = 0; q < 4; ++q) s->inflow_U[k][q] = 0;
+      continue;
+    }
+    conserved_of(st[0], st[1], twod ? st[2] : 0.0, st[3], s->cv, U4);
+    for (int q = 0; q < 4; ++q) s->inflow_U[k][q] = (long long)std::nearbyint(U4[q] * s->scale);
+  }
+  // upload the primitive fields chunk by chunk and build the equilibrium state
+  const size_t chunk = s->L.stage_cells;
+  std::vector<double> host(4 * chunk);
+  for (size_t first = 0; first < n; first += chunk) {
+    const size_t cnt = std::min(chunk, n - first);
+    for (size_t k = 0; k < cnt; ++k) {
+      host[k] = rho[first + k];
+      host[cnt + k] = ux[first + k];
+      host[2 * cnt + k] = twod ? uy[first + k] : 0.0;
+      host[3 * cnt + k] = p[first + k];
+    }
+    POND_HIP(hipMemcpyAsync(s->stage, host.data(), 4 * cnt * sizeof(double), hipMemcpyHostToDevice,
+                            s->stream));
+    POND_HIP(launch_init(c.dim, s->L.fp64, s->stage, n, first, cnt, s->scale, s->cv, s->n[0],
+                         s->U[0], s->stream));
+    POND_HIP(hipStreamSynchronize(s->stream));
+  }
+  POND_HIP(hipMemsetAsync(s->flag, 0, sizeof(int), s->stream));
+  POND_HIP(hipStreamSynchronize(s->stream));
+  s->cur = 0;
+  s->nstep = 0;
+  s->initialized = true;
+  // constant part of the step arguments
+  StepArgs& a = s->args;
+  a = StepArgs{};
+  a.nx = c.nx;
+  a.ny = c.ny;
+  for (int k = 0; k < 4; ++k) a.bc[k] = c.bc[k];
+  a.n_corr = c.n_corr;
+  a.limiter = c.limiter;
+  if (twod) {
+    a.tiles_x = (c.nx + kTX2 - 1) / kTX2;
+    a.tiles_y = (c.ny + kTY2 - 1) / kTY2;
+  } else {
+    a.tiles_x = (c.nx + kTX1 - 1) / kTX1;
+    a.tiles_y = 1;
+  }
+  a.scale = s->scale;
+  a.inv_scale = std::ldexp(1.0, -s->scale_bits);
+  a.cv = s->cv;
+  a.icv = 1.0 / s->cv;
+  a.geq = s->cv - 0.5 * c.dim;
+  a.lam = s->dt / s->dx;
+  // tau is tau1 / dt; with tau1 = tau dt all DUGKS coefficients depend on tau only
+  const double t = c.tau;
+  a.a_pre = (2.0 * t - 0.5) / (2.0 * t + 1.0);
+  a.b_upd = (2.0 * t - 1.0) / (2.0 * t + 1.0);
+  a.c_face1 = 4.0 * t / (4.0 * t + 1.0);
+  a.c_face2 = 1.0 / (4.0 * t + 1.0);
+  a.kappa = 0.5 * (1.0 / t - c.prandtl / t);  // (dt/2)(1/tau1 - 1/tau2) with tau2 = tau1/Pr
+  for (int k = 0; k < 4; ++k)
+    for (int q = 0; q < 4; ++q) a.inflow_U[k][q] = s->inflow_U[k][q];
+  a.cells = n;
+  a.flag = s->flag;
+  return POND_OK;
+}
+
+int pond_step(pond_state* s, int nsteps) {
+  if (!s || nsteps < 0) return fail(POND_ERR_INVALID, "bad arguments");
+  if (!s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
+  for (int k = 0; k < nsteps; ++k) {
+    StepArgs a = s->args;
+    a.n_in = s->n[s->cur];
+    a.n_out = s->n[1 - s->cur];
+    a.U_in = s->U[s->cur];
+    a.U_out = s->U[1 - s->cur];
+    POND_HIP(launch_step(s->cfg.dim, s->L.fp64, a, s->stream));
+    s->cur ^= 1;
+    s->nstep++;
+  }
+  return POND_OK;
+}
+
+int pond_moments(pond_state* s, double* rho, double* ux, double* uy, double* T) {
+  if (!s || !s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
+  int rc = sync_flag(s);
+  const size_t n = s->L.cells, chunk = s->L.stage_cells;
+  std::vector<double> host(4 * chunk);
+  double* outs[4] = {rho, ux, uy, T};
+  for (size_t first = 0; first < n; first += chunk) {
+    const size_t cnt = std::min(chunk, n - first);
+    POND_HIP(launch_moments(s->cfg.dim, s->U[s->cur], n, first, cnt, s->args.inv_scale,
+                            s->args.icv, s->stage, s->stream));
+    POND_HIP(hipMemcpyAsync(host.data(), s->stage, 4 * cnt * sizeof(double), hipMemcpyDeviceToHost,
+                            s->stream));
+    POND_HIP(hipStreamSynchronize(s->stream));
+    for (int q = 0; q < 4; ++q)
+      if (outs[q]) std::memcpy(outs[q] + first, host.data() + q * cnt, cnt * sizeof(double));
+  }
+  return rc;
+}
+
+static int totals128(pond_state* s, __int128 tot[4]) {
+  POND_HIP(launch_totals(s->U[s->cur], s->L.cells, s->L.red_blocks, s->red, s->stream));
+  std::vector<long long> host(size_t(s->L.red_blocks) * 8);
+  POND_HIP(hipMemcpyAsync(host.data(), s->red, host.size() * sizeof(long long),
+                          hipMemcpyDeviceToHost, s->stream));
+  POND_HIP(hipStreamSynchronize(s->stream));
+  for (int q = 0; q < 4; ++q) tot[q] = 0;
+  for (int b = 0; b < s->L.red_blocks; ++b)
+    for (int q = 0; q < 4; ++q) {
+      const unsigned __int128 hi = (unsigned __int128)(unsigned long long)host[(b * 4 + q) * 2];
+      const unsigned __int128 lo = (unsigned long long)host[(b * 4 + q) * 2 + 1];
+      tot[q] += (__int128)((hi << 64) | lo);
+    }
+  return POND_OK;
+}
+
+int pond_totals_fixed(pond_state* s, int64_t out[8], int* scale_bits) {
+  if (!s || !s->initialized || !out) return fail(POND_ERR_INVALID, "bad arguments");
+  int rc = sync_flag(s);
+  __int128 tot[4];
+  int r2 = totals128(s, tot);
+  if (r2) return r2;
+  for (int q = 0; q < 4; ++q) {
+    out[2 * q] = (int64_t)(tot[q] >> 64);
+    out[2 * q + 1] = (int64_t)(uint64_t)tot[q];
+  }
+  if (scale_bits) *scale_bits = s->scale_bits;
+  return rc;
+}
+
+int pond_totals(pond_state* s, double out[4]) {
+  if (!s || !s->initialized || !out) return fail(POND_ERR_INVALID, "bad arguments");
+  int rc = sync_flag(s);
+  __int128 tot[4];
+  int r2 = totals128(s, tot);
+  if (r2) return r2;
+  const double vol = s->cfg.dim == 2 ? s->dx * s->dx : s->dx;
+  for (int q = 0; q < 4; ++q) out[q] = std::ldexp((double)tot[q], -s->scale_bits) * vol;
+  return rc;
+}
+
+int pond_export_state(pond_state* s, double* f, double* g, double* frame) {
+  if (!s || !s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
+  int rc = sync_flag(s);
+  const size_t n = s->L.cells, chunk = s->L.stage_cells, rows = size_t(s->L.NP + 3);
+  const int QF = s->L.QF, QG = s->L.QG;
+  std::vector<double> host(rows * chunk);
+  for (size_t first = 0; first < n; first += chunk) {
+    const size_t cnt = std::min(chunk, n - first);
+    POND_HIP(launch_export(s->cfg.dim, s->L.fp64, s->n[s->cur], s->U[s->cur], n, first, cnt,
+                           s->args.inv_scale, s->args.icv, s->args.geq, s->stage, s->stream));
+    POND_HIP(hipMemcpyAsync(host.data(), s->stage, rows * cnt * sizeof(double),
+                            hipMemcpyDeviceToHost, s->stream));
+    POND_HIP(hipStreamSynchronize(s->stream));
+    for (int i = 0; i < QF; ++i)
+      if (f) std::memcpy(f + i * n + first, host.data() + i * cnt, cnt * sizeof(double));
+    for (int i = 0; i < QG; ++i)
+      if (g) std::memcpy(g + i * n + first, host.data() + (QF + i) * cnt, cnt * sizeof(double));
+    for (int i = 0; i < 3; ++i)
+      if (frame)
+        std::memcpy(frame + i * n + first, host.data() + (QF + QG + i) * cnt, cnt * sizeof(double));
+  }
+  return rc;
+}
+
+int pond_get_time(pond_state* s, double* dt, int64_t* nsteps) {
+  if (!s) return fail(POND_ERR_INVALID, "null state");
+  if (dt) *dt = s->dt;
+  if (nsteps) *nsteps = s->nstep;
+  return POND_OK;
+}
+
+namespace {
+struct CkptHeader {
+  char magic[8];
+  pond_config cfg;
+  double dt;
+  int64_t nstep;
+  int scale_bits;
+  int fp64;
+  uint64_t pop_bytes, led_bytes;
+};
+}  // namespace
+
+int pond_save(pond_state* s, const char* path) {
+  if (!s || !s->initialized || !path) return fail(POND_ERR_INVALID, "bad arguments");
+  POND_HIP(hipStreamSynchronize(s->stream));
+  CkptHeader h{};
+  std::memcpy(h.magic, "PONDCKP1", 8);
+  h.cfg = s->cfg;
+  h.dt = s->dt;
+  h.nstep = s->nstep;
+  h.scale_bits = s->scale_bits;
+  h.fp64 = s->L.fp64;
+  const size_t elt = s->L.fp64 ? 8 : 4;
+  h.pop_bytes = size_t(s->L.NP) * s->L.cells * elt;
+  h.led_bytes = 4 * s->L.cells * sizeof(long long);
+  std::vector<char> buf(h.pop_bytes + h.led_bytes);
+  POND_HIP(hipMemcpy(buf.data(), s->n[s->cur], h.pop_bytes, hipMemcpyDeviceToHost));
+  POND_HIP(hipMemcpy(buf.data() + h.pop_bytes, s->U[s->cur], h.led_bytes, hipMemcpyDeviceToHost));
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(POND_ERR_INVALID, std::string("cannot open ") + path);
+  const bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
+  std::fclose(fp);
+  return ok ? POND_OK : fail(POND_ERR_INVALID, "short write");
+}
+
+int pond_load(pond_state* s, const char* path) {
+  if (!s || !path) return fail(POND_ERR_INVALID, "bad arguments");
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(POND_ERR_INVALID, std::string("cannot open ") + path);
+  CkptHeader h{};
+  if (std::fread(&h, sizeof h, 1, fp) != 1 || std::memcmp(h.magic, "PONDCKP1", 8) != 0 ||
+      std::memcmp(&h.cfg, &s->cfg, sizeof(pond_config)) != 0) {
+    std::fclose(fp);
+    return fail(POND_ERR_INVALID, "checkpoint does not match this configuration");
+  }
+  std::vector<char> buf(h.pop_bytes + h.led_bytes);
+  const bool ok = std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
+  std::fclose(fp);
+  if (!ok) return fail(POND_ERR_INVALID, "short read");
+  // rebuild the constant step arguments from a neutral field, then overwrite
+  if (!s->initialized) {
+    std::vector<double> one(s->L.cells, 1.0), zero(s->L.cells, 0.0);
+    int rc = pond_init_fields(s, one.data(), zero.data(), zero.data(), one.data());
+    if (rc) return rc;
+  }
+  s->dt = h.dt;
+  s->nstep = h.nstep;
+  s->scale_bits = h.scale_bits;
+  s->scale = std::ldexp(1.0, h.scale_bits);
+  s->args.scale = s->scale;
+  s->args.inv_scale = std::ldexp(1.0, -h.scale_bits);
+  s->args.lam = s->dt / s->dx;
+  for (int k = 0; k < 4; ++k) {
+    const double* st = s->cfg.inflow[k];
+    double U4[4];
+    conserved_of(st[0], st[1], s->cfg.dim == 2 ? st[2] : 0.0, st[3], s->cv, U4);
+    for (int q = 0; q < 4; ++q)
+      s->args.inflow_U[k][q] = s->cfg.bc[k] == POND_BC_INFLOW ? (long long)std::nearbyint(U4[q] * s->scale) : 0;
+  }
+  s->cur = 0;
+  POND_HIP(hipMemcpy(s->n[0], buf.data(), h.pop_bytes, hipMemcpyHostToDevice));
+  POND_HIP(hipMemcpy(s->U[0], buf.data() + h.pop_bytes, h.led_bytes, hipMemcpyHostToDevice));
+  return POND_OK;
+}
+
+int pond_destroy(pond_state* s) {
+  if (!s) return POND_OK;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  delete s;
+  return e == hipSuccess ? POND_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+int pond_lattice_constants(double out[14]) {
+  if (!out) return fail(POND_ERR_INVALID, "null argument");
+  const double v[14] = {-kB, -kA, kA, kB, kWB, kWA, kWA, kWB, -kR3, 0.0, kR3, 1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+  std::memcpy(out, v, sizeof v);
+  return POND_OK;
+}
+
+}  // extern "C"

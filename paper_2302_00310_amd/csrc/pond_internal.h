@@ -1,0 +1,66 @@
+// Internal declarations shared by the HIP kernels and the host side of
+// libpond.so.  Not part of the public interface (include/pond.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pond {
+
+// Gauss--Hermite constants of Table I (T_L = 1), correctly rounded from the
+// closed forms.  D1Q4 nodes in ascending order: -B, -A, A, B with weights
+// WB, WA, WA, WB; D1Q3 nodes -R3, 0, R3 with weights 1/6, 2/3, 1/6.
+constexpr double kA = 0.7419637843027258;     // sqrt(3 - sqrt 6)
+constexpr double kB = 2.3344142183389773;     // sqrt(3 + sqrt 6)
+constexpr double kA2 = 0.5505102572168219;    // 3 - sqrt 6
+constexpr double kB2 = 5.449489742783178;     // 3 + sqrt 6
+constexpr double kWA = 0.4541241452319315;    // (3 + sqrt 6) / 12
+constexpr double kWB = 0.04587585476806849;   // (3 - sqrt 6) / 12
+constexpr double kKA = -0.13755667699048205;  // 1 / (2A (A^2 - B^2))
+constexpr double kKB = 0.04372063527294086;   // 1 / (2B (B^2 - A^2))
+constexpr double kR3 = 1.7320508075688772;    // sqrt 3
+
+// Tile shapes of the fused step kernel.
+constexpr int kTX2 = 16, kTY2 = 15;  // 2D: 240 cells, 255 x-faces, 256 y-faces
+constexpr int kTX1 = 255;            // 1D: 255 cells, 256 faces
+constexpr int kThreads = 256;
+
+// Everything one launch of the step kernel needs (passed by value).
+struct StepArgs {
+  int nx, ny;
+  int bc[4];
+  int n_corr, limiter;
+  int tiles_x, tiles_y;
+  double inv_scale;        // 2^-E: fixed-point unit of the conserved-moment ledger
+  double scale;            // 2^E
+  double cv, icv, geq;     // C_v, 1/C_v, C_v - D/2
+  double lam;              // dt / dx
+  double a_pre;            // (2 tau - dt/2) / (2 tau + dt)
+  double b_upd;            // (2 tau - dt) / (2 tau + dt)
+  double c_face1, c_face2; // 4 tau / (4 tau + dt), dt / (4 tau + dt)
+  double kappa;            // (dt/2) (1/tau1 - 1/tau2)
+  long long inflow_U[4][4];
+  size_t cells;            // nx * ny: stride between planes
+  const void* n_in;        // Qf + Qg planes of non-equilibrium populations
+  void* n_out;
+  const long long* U_in;   // 4 planes: rho, rho u_x, rho u_y, rho E (fixed point)
+  long long* U_out;
+  int* flag;               // bit 1: non-physical state, bit 2: ledger overflow
+};
+
+// Host-side launchers (defined in pond_kernels.hip).
+hipError_t launch_step(int dim, bool fp64, const StepArgs& a, hipStream_t st);
+hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,
+                       size_t count, double scale, double cv, void* n, long long* U,
+                       hipStream_t st);
+hipError_t launch_moments(int dim, const long long* U, size_t cells, size_t first, size_t count,
+                          double inv_scale, double icv, double* out, hipStream_t st);
+hipError_t launch_export(int dim, bool fp64, const void* n, const long long* U, size_t cells,
+                         size_t first, size_t count, double inv_scale, double icv, double geq,
+                         double* out, hipStream_t st);
+hipError_t launch_totals(const long long* U, size_t cells, int blocks, long long* out,
+                         hipStream_t st);
+
+}  // namespace pond

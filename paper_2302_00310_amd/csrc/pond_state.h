@@ -1,0 +1,50 @@
+// Device state of one solve (internal to libpond.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/pond.h"
+#include "pond_internal.h"
+
+namespace pond {
+
+constexpr size_t kStagingBytes = size_t(16) << 20;  // host<->device staging in the arena
+
+struct Layout {
+  int D = 2, QF = 16, QG = 9, NP = 25;
+  bool fp64 = false;
+  size_t cells = 0;
+  size_t pop_bytes = 0, led_bytes = 0, red_bytes = 0, stage_bytes = 0;
+  size_t stage_rows = 0, stage_cells = 0;
+  int red_blocks = 256;
+  size_t total = 0;
+};
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+int validate(const pond_config* c);
+Layout layout_of(const pond_config* c);
+
+}  // namespace pond
+
+struct pond_state {
+  pond_config cfg{};
+  pond::Layout L;
+  hipStream_t stream = nullptr;
+  void* n[2] = {nullptr, nullptr};        // non-equilibrium population planes (ping-pong)
+  long long* U[2] = {nullptr, nullptr};   // conserved-moment ledger planes (ping-pong)
+  int* flag = nullptr;
+  long long* red = nullptr;
+  double* stage = nullptr;
+  int cur = 0;
+  int64_t nstep = 0;
+  bool initialized = false;
+  double dt = 0.0, dx = 0.0, cv = 0.0, scale = 1.0;
+  int scale_bits = 0;
+  long long inflow_U[4][4] = {};
+  pond::StepArgs args{};
+};

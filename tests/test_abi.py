@@ -1,0 +1,103 @@
+"""CPU checks of the C interface: libpond.so loads, exports every function
+include/pond.h declares, carries the Table I constants, and rejects invalid
+configurations before touching a device."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from numpy.polynomial import hermite_e as He
+
+from paper_2302_00310_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pond():
+    from paper_2302_00310_amd import pond as p
+    if not os.path.exists(p.LIB_PATH):
+        from paper_2302_00310_amd.build import build
+        build()
+    p.load_library()
+    return p
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pond.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|size_t)\s+(pond_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_function_is_exported(pond):
+    names = declared_functions()
+    assert len(names) >= 18
+    lib = C.CDLL(pond.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(pond.exported_symbols()) == names
+
+
+def test_lattice_constants_are_gauss_hermite(pond):
+    c = pond.pond_lattice_constants()
+    x4, w4 = He.hermegauss(4)
+    x3, w3 = He.hermegauss(3)
+    s = math.sqrt(2 * math.pi)
+    np.testing.assert_allclose(c[0:4], x4, atol=1e-15)
+    np.testing.assert_allclose(c[4:8], w4 / s, atol=1e-16)
+    np.testing.assert_allclose(c[8:11], x3, atol=1e-15)
+    np.testing.assert_allclose(c[11:14], w3 / s, atol=1e-16)
+
+
+def _cfg(pond, **over):
+    wl = inputs.quadrants_2d(32, steps=1)
+    c = pond.make_config(wl)
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("field,value", [("dim", 3), ("nx", 0), ("gamma", 1.0), ("tau", 0.0),
+                                         ("prandtl", 1.5), ("prandtl", 0.0), ("cfl", -1.0),
+                                         ("n_corr", 9), ("limiter", 7), ("precision", 5),
+                                         ("lattice", 1)])
+def test_invalid_configs_are_rejected(pond, field, value):
+    c = _cfg(pond, **{field: value})
+    assert pond.pond_state_bytes(c) == 0
+    h = C.c_void_p()
+    rc = pond.load_library().pond_create(C.byref(c), None, 0, None, C.byref(h))
+    assert rc == -1 and not h.value
+
+
+def test_half_periodic_axis_is_rejected(pond):
+    c = _cfg(pond)
+    c.bc[0] = 0
+    c.bc[1] = 1
+    assert pond.pond_state_bytes(c) == 0
+
+
+def test_grad_transform_reports_unsupported(pond):
+    c = _cfg(pond, transform=1)
+    h = C.c_void_p()
+    assert pond.load_library().pond_create(C.byref(c), None, 0, None, C.byref(h)) == -6
+
+
+def test_state_bytes_scale_with_precision(pond):
+    c64 = _cfg(pond, precision=0)
+    c32 = _cfg(pond, precision=1)
+    b64, b32 = pond.pond_state_bytes(c64), pond.pond_state_bytes(c32)
+    cells = 32 * 32
+    assert b64 - b32 >= 2 * 25 * 4 * cells
+    assert b32 >= 2 * (25 * 4 + 32) * cells
+
+
+def test_no_device_is_an_error_not_a_fallback(pond):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    c = _cfg(pond)
+    h = C.c_void_p()
+    rc = pond.load_library().pond_create(C.byref(c), C.c_void_p(256), 1 << 30, None, C.byref(h))
+    assert rc == -3

@@ -1,0 +1,205 @@
+"""Parity of the HIP PonD step (libpond.so, called through its C interface)
+with the FP64 CPU oracle on the same seeded inputs.
+
+Bars: the FP64 path agrees to <= 1e-12 (scale-relative max error); the mixed
+path (FP32 populations, FP64 gauge and fluxes) to <= 1e-5 relative L2 on rho,
+u and T.  Small grids are compared cell by cell (several tiles and a ragged
+tail); the full benchmark grids are compared on sampled cells whose whole
+domain of dependence the oracle computes on a window."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_00310_amd import inputs
+from tests.gpu_common import moment_errors, rel_err, rel_l2, solver, window_samples
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = 0, 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2302_00310_amd import pond
+    pond.load_library()
+    yield
+
+
+def _pops_err(s, o):
+    f, g, fr = s.export_state()
+    fo, go, fro = o.get_state()
+    return max(rel_err(f, fo), rel_err(g, go), rel_err(fr, fro))
+
+
+def test_sod_1d_fp64_every_step():
+    """400 cells, zero-gradient ends, 200 steps, moments compared every step."""
+    wl = inputs.sod_1d(400, 200)
+    s = solver(wl, FP64)
+    o = oracle.Oracle(wl)
+    assert abs(s.dt / o.dt - 1.0) < 1e-15
+    worst = 0.0
+    for step in range(200):
+        s.step(1)
+        o.step(1)
+        e = moment_errors(s.moments(), o.moments())
+        worst = max(worst, *e.values())
+        assert max(e.values()) <= 1e-12, (step, e)
+    assert _pops_err(s, o) <= 1e-12
+    print("sod_1d worst", worst)
+
+
+@pytest.mark.parametrize("case", ["vortex", "quadrants", "shu_osher", "vortex_ncorr", "quadrants_minmod"])
+def test_2d_fp64_small_grids(case):
+    if case.startswith("vortex"):
+        wl = inputs.vortex_2d(48, steps=1, noise=1e-3, ny=40)
+    elif case.startswith("quadrants"):
+        wl = inputs.quadrants_2d(35, steps=1, seed=3, ny=33)
+    else:
+        wl = inputs.shu_osher_2d(64, 20, steps=1)
+    kw = {}
+    if case.endswith("ncorr"):
+        kw["n_corr"] = 2
+    if case.endswith("minmod"):
+        kw["limiter"] = 1
+    s = solver(wl, FP64, **kw)
+    o = oracle.Oracle(wl, **kw)
+    for _ in range(4):
+        s.step(5)
+        o.step(5)
+        e = moment_errors(s.moments(), o.moments())
+        assert max(e.values()) <= 1e-12, e
+    assert _pops_err(s, o) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["vortex", "quadrants", "shu_osher"])
+def test_2d_mixed_small_grids(case):
+    if case == "vortex":
+        wl = inputs.vortex_2d(48, steps=1, noise=1e-3, ny=40)
+    elif case == "quadrants":
+        wl = inputs.quadrants_2d(35, steps=1, seed=3, ny=33)
+    else:
+        wl = inputs.shu_osher_2d(64, 20, steps=1)
+    s = solver(wl, MIXED)
+    o = oracle.Oracle(wl)
+    s.step(60)
+    o.step(60)
+    e = moment_errors(s.moments(), o.moments(), l2=True)
+    assert max(e.values()) <= 1e-5, e
+
+
+def test_1d_mixed():
+    wl = inputs.sod_1d(400, 200)
+    s = solver(wl, MIXED)
+    o = oracle.Oracle(wl)
+    s.step(200)
+    o.step(200)
+    e = moment_errors(s.moments(), o.moments(), l2=True)
+    assert max(e.values()) <= 1e-5, e
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+@pytest.mark.parametrize("mach", [0.0, 2.0, 30.0])
+def test_uniform_flow_stays_uniform(precision, mach):
+    T = 0.7
+    sp = mach * np.sqrt(1.4 * T)
+    wl = inputs.uniform_2d(40, 33, 0.8, 0.6 * sp, -0.8 * sp, 0.8 * T, prandtl=0.7)
+    s = solver(wl, precision)
+    s.step(50)
+    r, ux, uy, TT = s.moments()
+    tol = 1e-13 if precision == FP64 else 1e-6
+    assert np.abs(r - 0.8).max() <= tol * 0.8
+    assert np.abs(TT - T).max() <= tol * T * max(1.0, mach)
+    assert np.abs(ux - 0.6 * sp).max() <= tol * max(1.0, sp)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_exact_conservation_periodic(precision):
+    """The fixed-point ledger of (rho, rho u, rho E) is updated by one rounded
+    flux per face, added to one cell and subtracted from the other: the
+    integer totals do not change at all."""
+    wl = inputs.vortex_2d(64, steps=1, noise=1e-2, ny=47)
+    s = solver(wl, precision)
+    t0 = s.totals_fixed()
+    s.step(40)
+    t1 = s.totals_fixed()
+    assert t0 == t1
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_run_twice_bitwise(precision):
+    wl = inputs.quadrants_2d(70, steps=1, seed=9, ny=50)
+    a = solver(wl, precision)
+    b = solver(wl, precision)
+    a.step(15)
+    b.step(15)
+    fa, ga, ra = a.export_state()
+    fb, gb, rb = b.export_state()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb) and np.array_equal(ra, rb)
+
+
+def test_checkpoint_resume_bitwise(tmp_path):
+    wl = inputs.quadrants_2d(40, steps=1, seed=4, ny=36)
+    a = solver(wl, MIXED)
+    a.step(20)
+    from paper_2302_00310_amd import pond
+    path = str(tmp_path / "ck.bin")
+    a.step(5)
+    pond.pond_save(a.h, path)
+    a.step(10)
+    b = solver(wl, MIXED, init=False)
+    pond.pond_load(b.h, path)
+    b.step(10)
+    assert all(np.array_equal(x, y) for x, y in zip(a.export_state(), b.export_state()))
+
+
+def test_transpose_symmetry_fp64():
+    wl = inputs.quadrants_2d(36, steps=1, seed=11, prandtl=0.7)
+    wt = inputs.quadrants_2d(36, steps=1, seed=11, prandtl=0.7)
+    wt.rho, wt.p = wl.rho.T.copy(), wl.p.T.copy()
+    wt.ux, wt.uy = wl.uy.T.copy(), wl.ux.T.copy()
+    a = solver(wl, FP64)
+    b = solver(wt, FP64)
+    a.step(10)
+    b.step(10)
+    ma, mb = a.moments(), b.moments()
+    assert rel_err(mb[0], ma[0].T) < 1e-13
+    assert rel_err(mb[1], ma[2].T) < 1e-12
+    assert rel_err(mb[3], ma[3].T) < 1e-13
+
+
+# ---- full benchmark grids, sampled cells ----------------------------------
+FULL = {
+    "vortex_256": lambda: inputs.vortex_2d(256),
+    "quadrants_2048": lambda: inputs.quadrants_2d(2048),
+    "shu_osher_4096x1024": lambda: inputs.shu_osher_2d(),
+}
+
+
+def _sample_points(wl, rng):
+    nx, ny = wl.nx, wl.ny
+    pts = [(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (nx // 2 - 1, ny // 2),
+           (0, ny // 2), (nx - 1, 3)]
+    pts += [(int(rng.integers(nx)), int(rng.integers(ny))) for _ in range(4)]
+    return pts
+
+
+@pytest.mark.parametrize("name", list(FULL))
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_full_size_sampled_cells(name, precision):
+    wl = FULL[name]()
+    steps = 6
+    pts = _sample_points(wl, np.random.Generator(np.random.PCG64(17)))
+    ref, dt = window_samples(wl, pts, steps)
+    s = solver(wl, precision)
+    assert abs(s.dt / dt - 1.0) < 1e-15
+    s.step(steps)
+    m = s.moments()
+    got = np.array([[float(a[y, x]) for a in m] for (x, y) in pts])
+    if precision == FP64:
+        for k in range(4):
+            assert rel_err(got[:, k], ref[:, k], floor=1.0 if k in (1, 2) else 1e-300) <= 1e-12, (k, got[:, k], ref[:, k])
+    else:
+        for k in range(4):
+            assert rel_l2(got[:, k], ref[:, k]) <= 1e-5 or np.max(np.abs(got[:, k] - ref[:, k])) <= 1e-6

@@ -136,7 +136,8 @@ class Brute:
                         rec(0, 2, 1, 0, 0, mp.mpf(1) / 2 - lam * vn / 2)
                     rr = rec(1, 0, 3, 7, 6, -mp.mpf(1) / 2 - lam * vn / 2) if self.D == 2 else \
                         rec(1, 0, 3, 0, 0, -mp.mpf(1) / 2 - lam * vn / 2)
-                    out.append(rl if vn > 0 else (rr if vn < 0 else (rl + rr) / 2))
+                    band = mp.mpf('1e-11') * rt
+                    out.append(rl if vn > band else (rr if vn < -band else (rl + rr) / 2))
                 bars.append(out)
             rho_b, ub, vb, Tb = self.moments(bars[0], bars[1], lF)
             if pss < self.n_corr:
