@@ -1,0 +1,169 @@
+"""Benchmark of the PonD time step on one MI355X.
+
+Workload: the four-quadrant 2D Riemann stand-in, 2048 x 2048 cells,
+D2Q16 f + D2Q9 g, zero-gradient boundaries, Pr = 0.71, tau = 0.55, seeded
+states (seed 3).  The headline value is the mixed-precision step (FP32
+populations, FP64 gauge and conservative fluxes); the FP64 step is timed on
+the same grid for the mixed/FP64 speed-up.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# gfx950: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32
+# is disabled in this build, so FP32 and FP64 vector ops share this peak.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+# Algorithmic bytes per 2D cell-update: the persistent state read once and
+# written once -- 25 non-equilibrium populations plus the 4 x 64-bit
+# conserved-moment ledger.
+BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
+
+
+def flops_per_cell_2d(n_corr: int = 0) -> int:
+    """Floating-point operations of one 2D cell-update as the kernel's
+    algorithm specifies them (FMA = 2).  Per face (two per cell), for each
+    of the 8 stencil cells: the Lagrange factors of the f transform
+    (2 x 4 points x 15) plus its 2 x 64 FMA application, and the same for g
+    (2 x 3 points x 10, 2 x 27 FMA); reconstruction (25 populations x 24);
+    FP64 face moments (16 x 10 + 9); face equilibrium (f: 2 x 4 points x 23,
+    g: 2 x 3 points x 16, 25 x 4 for the products and the inversion);
+    conserved fluxes (16 x 12 + 9 x 3).  Per cell: four face-to-cell
+    transforms and one re-gauge (5 x (376 + 168)), flux products and update
+    (25 x 8), two quasi-equilibrium half steps (2 x 300), phi-bar-plus and
+    frames (60)."""
+    f_tf = 2 * 4 * 15 + 2 * 64 * 2
+    g_tf = 2 * 3 * 10 + 2 * 27 * 2
+    stencil = 8 * (f_tf + g_tf)
+    per_pass = stencil + 25 * 24 + (16 * 10 + 9)
+    face = (1 + n_corr) * per_pass + (2 * 4 * 23 + 2 * 3 * 16 + 25 * 4) + (16 * 12 + 9 * 3)
+    cell = 5 * (f_tf + g_tf) + 25 * 8 + 2 * 300 + 60
+    return 2 * face + cell
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--n", type=int, default=2048, help="grid side")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-mb", type=int, default=0,
+                   help="after timing, copy this many MiB device-to-device (counter calibration)")
+    return p.parse_args()
+
+
+def time_path(wl, precision, steps, warmup):
+    import torch
+    from paper_2302_00310_amd import pond
+    s = pond.Solver(wl, precision=precision)
+    stream = torch.cuda.current_stream()
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / steps
+    rc, _ = pond.pond_moments(s.h, s.n)  # surfaces any non-physical state
+    pond.check(rc)
+    s.close()
+    return wall, kern_ms
+
+
+def cpu_baseline(wl_full, seconds):
+    """The FP64 oracle as it stands, on the host cores, on a 256 x 256 window
+    of the same workload (domain centre), advanced with the full grid's dt."""
+    import oracle
+    from paper_2302_00310_amd import inputs
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = oracle.set_threads(cores)
+    dt = oracle.cfl_dt(wl_full)
+    n = 256
+    w, _ = inputs.window(wl_full, wl_full.nx // 2 - n // 2, wl_full.ny // 2 - n // 2, n, n)
+    o = oracle.Oracle(w, dt=dt)
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    steps = max(1, int(seconds / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    o.step(steps)
+    el = time.perf_counter() - t0
+    return {"value": n * n * steps / el, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n}x{n} window at the centre of the 2048^2 quadrant workload, "
+                      f"{steps} FP64 steps in {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2302_00310_amd import inputs, pond
+    pond.load_library()
+    wl = inputs.quadrants_2d(a.n, steps=a.steps)
+    cells = wl.nx * wl.ny
+
+    wall_m, kern_m = time_path(wl, pond.POND_MIXED, a.steps, a.warmup)
+    value = cells * a.steps / wall_m
+    out = {
+        "metric": "cell-updates/s mixed vs FP64 step (% HBM roofline); p50/p99 solve latency",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * wall_m / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"four-quadrant 2D Riemann stand-in, {a.n}x{a.n}, D2Q16+D2Q9, "
+                               "zero-gradient, Pr=0.71, tau=0.55, seed 3, mixed precision "
+                               "(FP32 populations, FP64 gauge/fluxes), n_corr=0",
+                   "cells": cells},
+    }
+    flops = flops_per_cell_2d(0)
+    achieved_tf = flops * cells / (kern_m * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
+                       "traffic": None, "kernel": "step_kernel<2,float>",
+                       "kernel_ms": kern_m, "flops_per_cell": flops}
+    hbm = BYTES_PER_CELL["mixed"] * cells / (kern_m * 1e-3) / 1e9
+    out["hbm_roofline"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": hbm / HBM_PEAK_GBS, "bytes_per_cell": BYTES_PER_CELL["mixed"]}
+    if not a.no_fp64:
+        wall_d, kern_d = time_path(wl, pond.POND_FP64, a.steps, a.warmup)
+        v64 = cells * a.steps / wall_d
+        out["fp64"] = {"value": v64, "unit": "cell-updates/s", "ms_per_step": 1e3 * wall_d / a.steps,
+                       "kernel_ms": kern_d,
+                       "hbm_frac": BYTES_PER_CELL["fp64"] * cells / (kern_d * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "alu_frac": flops * cells / (kern_d * 1e-3) / 1e12 / VALU_PEAK_TFLOPS}
+        out["mixed_over_fp64"] = value / v64
+    if a.copy_mb:
+        x = torch.empty(a.copy_mb << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
