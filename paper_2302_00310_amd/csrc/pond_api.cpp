@@ -88,7 +88,7 @@ Layout layout_of(const pond_config* c) {
   L.stage_rows = size_t(std::max(4, L.NP + 3));
   L.stage_cells = std::min(L.cells, size_t(kStagingBytes / (8 * L.stage_rows)));
   L.stage_bytes = align256(L.stage_rows * L.stage_cells * 8);
-  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 256 + L.red_bytes + L.stage_bytes;
+  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.red_bytes + L.stage_bytes;
   return L;
 }
 
@@ -171,6 +171,7 @@ int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, voi
   s->U[0] = reinterpret_cast<long long*>(p); p += L.led_bytes;
   s->U[1] = reinterpret_cast<long long*>(p); p += L.led_bytes;
   s->flag = reinterpret_cast<int*>(p); p += 256;
+  s->inflow_dev = reinterpret_cast<long long*>(p); p += 256;
   s->red = reinterpret_cast<long long*>(p); p += L.red_bytes;
   s->stage = reinterpret_cast<double*>(p);
   s->dx = cfg->dx > 0.0 ? cfg->dx : 1.0 / cfg->nx;
@@ -274,8 +275,10 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   a.c_face1 = 4.0 * t / (4.0 * t + 1.0);
   a.c_face2 = 1.0 / (4.0 * t + 1.0);
   a.kappa = 0.5 * (1.0 / t - c.prandtl / t);  // (dt/2)(1/tau1 - 1/tau2) with tau2 = tau1/Pr
-  for (int k = 0; k < 4; ++k)
-    for (int q = 0; q < 4; ++q) a.inflow_U[k][q] = s->inflow_U[k][q];
+  POND_HIP(hipMemcpyAsync(s->inflow_dev, s->inflow_U, sizeof(s->inflow_U), hipMemcpyHostToDevice,
+                          s->stream));
+  POND_HIP(hipStreamSynchronize(s->stream));
+  a.inflow = s->inflow_dev;
   a.cells = n;
   a.flag = s->flag;
   return POND_OK;
@@ -455,8 +458,9 @@ int pond_load(pond_state* s, const char* path) {
     double U4[4];
     conserved_of(st[0], st[1], s->cfg.dim == 2 ? st[2] : 0.0, st[3], s->cv, U4);
     for (int q = 0; q < 4; ++q)
-      s->args.inflow_U[k][q] = s->cfg.bc[k] == POND_BC_INFLOW ? (long long)std::nearbyint(U4[q] * s->scale) : 0;
+      s->inflow_U[k][q] = s->cfg.bc[k] == POND_BC_INFLOW ? (long long)std::nearbyint(U4[q] * s->scale) : 0;
   }
+  POND_HIP(hipMemcpy(s->inflow_dev, s->inflow_U, sizeof(s->inflow_U), hipMemcpyHostToDevice));
   s->cur = 0;
   POND_HIP(hipMemcpy(s->n[0], buf.data(), h.pop_bytes, hipMemcpyHostToDevice));
   POND_HIP(hipMemcpy(s->U[0], buf.data() + h.pop_bytes, h.led_bytes, hipMemcpyHostToDevice));

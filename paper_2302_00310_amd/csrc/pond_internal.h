@@ -41,7 +41,7 @@ struct StepArgs {
   double b_upd;            // (2 tau - dt) / (2 tau + dt)
   double c_face1, c_face2; // 4 tau / (4 tau + dt), dt / (4 tau + dt)
   double kappa;            // (dt/2) (1/tau1 - 1/tau2)
-  long long inflow_U[4][4];
+  const long long* inflow; // device table [side][q] of the inflow states' fixed-point moments
   size_t cells;            // nx * ny: stride between planes
   const void* n_in;        // Qf + Qg planes of non-equilibrium populations
   void* n_out;

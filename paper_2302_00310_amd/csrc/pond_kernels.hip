@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "pond_internal.h"
 
@@ -30,6 +31,16 @@ namespace {
 constexpr int BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1;
 constexpr int LIM_MINMOD = 1;
 constexpr double kTieBand = 1e-11;  // |v_n| <= kTieBand sqrt(T_F): upwind tie
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<B + 1, E>(f);
+  }
+}
 
 // --------------------------------------------------------------------------
 // Lattice constants (Table I) as compile-time values.
@@ -51,87 +62,149 @@ __device__ __forceinline__ constexpr T weight(int k) {
   }
 }
 
-// Lagrange basis polynomials on the lattice nodes, out[k] = l_k(x).
-template <typename T>
-__device__ __forceinline__ void lagrange(T x, T (&out)[4]) {
-  // nodes -B, -A, A, B:  l_{+-B} = KB (x^2 - A^2)(B +- x),  l_{+-A} = KA (x^2 - B^2)(A +- x)
+// Per-point factors of the Lagrange basis on the lattice nodes: l_k(x) is a
+// product of a node-pair factor and one linear term, lag_entry<k>().
+template <int Q1, typename T>
+struct LagPoint {
+  T x, p, q;  // D1Q4: p = KB (x^2 - A^2), q = KA (x^2 - B^2); D1Q3: p = x / 6, q = x^2 / 3
+};
+template <int Q1, typename T>
+__device__ __forceinline__ LagPoint<Q1, T> lag_point(T x) {
+  LagPoint<Q1, T> r;
+  r.x = x;
   const T x2 = x * x;
-  const T p = (x2 - T(kA2)) * T(kKB);
-  const T q = (x2 - T(kB2)) * T(kKA);
-  out[0] = p * (T(kB) - x);
-  out[1] = q * (T(kA) - x);
-  out[2] = q * (T(kA) + x);
-  out[3] = p * (T(kB) + x);
+  if constexpr (Q1 == 4) {
+    r.p = (x2 - T(kA2)) * T(kKB);
+    r.q = (x2 - T(kB2)) * T(kKA);
+  } else {
+    r.p = x * T(1.0 / 6.0);
+    r.q = x2 * T(1.0 / 3.0);
+  }
+  return r;
 }
-template <typename T>
-__device__ __forceinline__ void lagrange(T x, T (&out)[3]) {
-  // nodes -R3, 0, R3:  l_{+-R3} = x (x +- R3) / 6,  l_0 = 1 - x^2 / 3
-  const T h = x * T(1.0 / 6.0);
-  out[0] = h * (x - T(kR3));
-  out[1] = T(1) - x * x * T(1.0 / 3.0);
-  out[2] = h * (x + T(kR3));
-}
-
-// One-dimensional factor of the moment-matching map (App. B): with
-// xi_m = s c_m + d the source velocity written in the target frame's
-// centred, scaled coordinates, A[k][m] = l_k(xi_m).
 template <int Q1, typename T>
-__device__ __forceinline__ void tf_factor(T s, T d, T (&A)[Q1][Q1]) {
-  T l[Q1];
-#pragma unroll
-  for (int m = 0; m < Q1; ++m) {
-    lagrange(s * node<Q1, T>(m) + d, l);
-#pragma unroll
-    for (int k = 0; k < Q1; ++k) A[k][m] = l[k];
+__device__ __forceinline__ T lag_entry(int k, const LagPoint<Q1, T>& L) {
+  if constexpr (Q1 == 4) {
+    return k == 0 ? L.p * (T(kB) - L.x) : k == 1 ? L.q * (T(kA) - L.x)
+         : k == 2 ? L.q * (T(kA) + L.x) : L.p * (T(kB) + L.x);
+  } else {
+    return k == 0 ? L.p * (L.x - T(kR3)) : k == 1 ? T(1) - L.q : L.p * (L.x + T(kR3));
   }
 }
 
-template <int Q1, typename T>
-__device__ __forceinline__ void tf_apply1(const T (&A)[Q1][Q1], const T* in, T* out) {
-#pragma unroll
-  for (int k = 0; k < Q1; ++k) {
-    T acc = A[k][0] * in[0];
-#pragma unroll
-    for (int m = 1; m < Q1; ++m) acc += A[k][m] * in[m];
-    out[k] = acc;
-  }
-}
-
-// Transform populations of one lattice (Q1 nodes per axis) from a frame with
-// (sqrt T, u) to the target frame given by (1/sqrt T', u').
+// Moment-matching map (App. B) of one lattice's populations from a frame
+// with (sqrt T, u) to the frame with (1/sqrt T', u'): on the tensor lattice
+// G = A_x (x) A_y with A[k][m] = l_k(xi_m), xi_m = s c_m + d, s = sqrt(T/T'),
+// d = (u - u')/sqrt(T').  Applied factor by factor, coefficient rows formed
+// on the fly so that only the point factors stay in registers.
 template <int D, int Q1, typename T>
 __device__ __forceinline__ void transform(double rt_src, double ux_src, double uy_src,
                                           double irt_dst, double ux_dst, double uy_dst,
                                           const T* in, T* out) {
   const T s = T(rt_src * irt_dst);
+  const T dx = T((ux_src - ux_dst) * irt_dst);
   if constexpr (D == 1) {
-    T Ax[Q1][Q1];
-    tf_factor<Q1, T>(s, T((ux_src - ux_dst) * irt_dst), Ax);
-    tf_apply1<Q1, T>(Ax, in, out);
+    LagPoint<Q1, T> X[Q1];
+#pragma unroll
+    for (int m = 0; m < Q1; ++m) X[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dx);
+#pragma unroll
+    for (int k = 0; k < Q1; ++k) {
+      T acc = lag_entry<Q1, T>(k, X[0]) * in[0];
+#pragma unroll
+      for (int m = 1; m < Q1; ++m) acc += lag_entry<Q1, T>(k, X[m]) * in[m];
+      out[k] = acc;
+    }
   } else {
-    // y factor first, then x: keeps one coefficient matrix live at a time
-    T Ay[Q1][Q1], Y[Q1][Q1];
-    tf_factor<Q1, T>(s, T((uy_src - uy_dst) * irt_dst), Ay);
+    T Y[Q1][Q1];  // Y[mx][ky] = sum_my A_y[ky][my] in[mx + Q1 my]
+    {
+      LagPoint<Q1, T> E[Q1];
+      const T dy = T((uy_src - uy_dst) * irt_dst);
 #pragma unroll
-    for (int mx = 0; mx < Q1; ++mx)
+      for (int m = 0; m < Q1; ++m) E[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dy);
 #pragma unroll
       for (int ky = 0; ky < Q1; ++ky) {
-        T acc = Ay[ky][0] * in[mx];
+        T row[Q1];
 #pragma unroll
-        for (int my = 1; my < Q1; ++my) acc += Ay[ky][my] * in[mx + Q1 * my];
-        Y[mx][ky] = acc;
+        for (int my = 0; my < Q1; ++my) row[my] = lag_entry<Q1, T>(ky, E[my]);
+#pragma unroll
+        for (int mx = 0; mx < Q1; ++mx) {
+          T acc = row[0] * in[mx];
+#pragma unroll
+          for (int my = 1; my < Q1; ++my) acc += row[my] * in[mx + Q1 * my];
+          Y[mx][ky] = acc;
+        }
       }
-    T Ax[Q1][Q1];
-    tf_factor<Q1, T>(s, T((ux_src - ux_dst) * irt_dst), Ax);
+    }
+    LagPoint<Q1, T> X[Q1];
 #pragma unroll
-    for (int kx = 0; kx < Q1; ++kx)
+    for (int m = 0; m < Q1; ++m) X[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dx);
+#pragma unroll
+    for (int kx = 0; kx < Q1; ++kx) {
+      T row[Q1];
+#pragma unroll
+      for (int mx = 0; mx < Q1; ++mx) row[mx] = lag_entry<Q1, T>(kx, X[mx]);
 #pragma unroll
       for (int ky = 0; ky < Q1; ++ky) {
-        T acc = Ax[kx][0] * Y[0][ky];
+        T acc = row[0] * Y[0][ky];
 #pragma unroll
-        for (int mx = 1; mx < Q1; ++mx) acc += Ax[kx][mx] * Y[mx][ky];
+        for (int mx = 1; mx < Q1; ++mx) acc += row[mx] * Y[mx][ky];
         out[kx + Q1 * ky] = acc;
       }
+    }
+  }
+}
+
+// The same map restricted to the outputs whose transverse index (i_y for an
+// x-face, i_x for a y-face) lies in [K0, K0 + NK); out is indexed
+// j = n + Q1 t (n: normal index, t = transverse index - K0).  The transverse
+// factor is applied first, so only the NK needed rows of it are formed.
+template <int D, int Q1, typename T, int AXIS, int K0, int NK>
+__device__ __forceinline__ void transform_part(double rt_src, double ux_src, double uy_src,
+                                               double irt_dst, double ux_dst, double uy_dst,
+                                               const T* in, T* out) {
+  if constexpr (D == 1) {
+    transform<D, Q1, T>(rt_src, ux_src, uy_src, irt_dst, ux_dst, uy_dst, in, out);
+  } else {
+    const T s = T(rt_src * irt_dst);
+    const T dn = T(((AXIS == 0 ? ux_src : uy_src) - (AXIS == 0 ? ux_dst : uy_dst)) * irt_dst);
+    const T dt = T(((AXIS == 0 ? uy_src : ux_src) - (AXIS == 0 ? uy_dst : ux_dst)) * irt_dst);
+    // stride of the normal / transverse axis in the population index
+    constexpr int SN = AXIS == 0 ? 1 : Q1, ST = AXIS == 0 ? Q1 : 1;
+    T Z[NK][Q1];  // Z[t][mn] = sum_mt A_t[K0 + t][mt] in[mn SN + mt ST]
+    {
+      LagPoint<Q1, T> E[Q1];
+#pragma unroll
+      for (int m = 0; m < Q1; ++m) E[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dt);
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        T row[Q1];
+#pragma unroll
+        for (int mt = 0; mt < Q1; ++mt) row[mt] = lag_entry<Q1, T>(K0 + t, E[mt]);
+#pragma unroll
+        for (int mn = 0; mn < Q1; ++mn) {
+          T acc = row[0] * in[mn * SN];
+#pragma unroll
+          for (int mt = 1; mt < Q1; ++mt) acc += row[mt] * in[mn * SN + mt * ST];
+          Z[t][mn] = acc;
+        }
+      }
+    }
+    LagPoint<Q1, T> X[Q1];
+#pragma unroll
+    for (int m = 0; m < Q1; ++m) X[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dn);
+#pragma unroll
+    for (int n = 0; n < Q1; ++n) {
+      T row[Q1];
+#pragma unroll
+      for (int mn = 0; mn < Q1; ++mn) row[mn] = lag_entry<Q1, T>(n, X[mn]);
+#pragma unroll
+      for (int t = 0; t < NK; ++t) {
+        T acc = row[0] * Z[t][0];
+#pragma unroll
+        for (int mn = 1; mn < Q1; ++mn) acc += row[mn] * Z[t][mn];
+        out[n + Q1 * t] = acc;
+      }
+    }
   }
 }
 
@@ -141,12 +214,11 @@ template <int Q1, typename T>
 __device__ __forceinline__ void eq_factor(T s, T d, T (&out)[Q1]) {
 #pragma unroll
   for (int k = 0; k < Q1; ++k) out[k] = T(0);
-  T l[Q1];
 #pragma unroll
   for (int m = 0; m < Q1; ++m) {
-    lagrange(s * node<Q1, T>(m) + d, l);
+    const LagPoint<Q1, T> L = lag_point<Q1, T>(s * node<Q1, T>(m) + d);
 #pragma unroll
-    for (int k = 0; k < Q1; ++k) out[k] += l[k] * weight<Q1, T>(m);
+    for (int k = 0; k < Q1; ++k) out[k] += lag_entry<Q1, T>(k, L) * weight<Q1, T>(m);
   }
 }
 
@@ -158,7 +230,12 @@ __device__ __forceinline__ T limit(int kind, T a, T b) {
     return a > T(0) ? fmin(a, b) : fmax(a, b);
   }
   const T den = fabs(a) + fabs(b);
-  return den > T(0) ? (a * fabs(b) + fabs(a) * b) / den : T(0);
+  if constexpr (sizeof(T) == 4) {
+    // FP32: hardware reciprocal (1 ulp) instead of an IEEE division
+    return den > T(0) ? (a * fabs(b) + fabs(a) * b) * __builtin_amdgcn_rcpf(den) : T(0);
+  } else {
+    return den > T(0) ? (a * fabs(b) + fabs(a) * b) / den : T(0);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -297,10 +374,9 @@ template <int D, typename T>
 struct Smem {
   using G = Geo<D>;
   T P[G::NP * G::NH];          // phi-bar-plus of the halo tile, plane-major
-  double U[G::NH], V[G::NH], TT[G::NH], RT[G::NH];  // cell frames (u_x, u_y, T, sqrt T)
+  double U[G::NH], V[G::NH], RT[G::NH];  // cell frames (u_x, u_y, sqrt T)
   T F[G::NP * G::NF];          // face populations phi^{lambda_F}
   double FU[G::NF], FV[G::NF], FRT[G::NF];          // face frames
-  long long Psi[4 * G::NF];    // rounded conserved fluxes of the faces
 };
 
 // Halo coordinates of tile slot k: interior slots first (thread k owns
@@ -358,12 +434,8 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
     if (side < 0) sy = resolve(gy, a.ny, a.bc[2], a.bc[3], &side, 2);
   }
   if (side >= 0) {
-    // select the side's inflow state with constant indices (no indexed copy of the arguments)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (side == k)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) U[q] = a.inflow_U[k][q];
+    for (int q = 0; q < 4; ++q) U[q] = a.inflow[4 * side + q];
 #pragma unroll
     for (int i = 0; i < NP; ++i) n[i] = T(0);
     return;
@@ -382,110 +454,178 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
 // --------------------------------------------------------------------------
 
 // MUSCL reconstruction at the departure point x_b - v dt/2 (eq. InterfacePop)
-// of one lattice's populations, from the upwind cell by the sign of the
-// normal velocity; an exact tie takes the mean of both upwind values.  The
-// stencil is transformed into the face frame one cell at a time and folded
-// into the running left- and right-upwind reconstructions.
-template <int D, int Q1, typename T, int AXIS>
+// of the populations of one lattice whose transverse index lies in
+// [K0, K0 + NK) (local index j = n + Q1 t), from the upwind cell by the sign
+// of the normal velocity.  A normal velocity within kTieBand of the face
+// thermal speed is a tie (rounding noise around a fluid at rest cannot pick a
+// side), and a tie takes the mean of both upwind reconstructions.  The
+// stencil is transformed into the face frame one cell at a time; the upwind
+// operands of the two limiters are selected per population, so each
+// population costs one normal and one transverse limiter; ties take a second
+// pass.
+template <int D, int Q1, typename T, int AXIS, int K0, int NK>
 __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>& sm,
                                             const int (&st)[Geo<D>::NS], int plane0, double rtF,
                                             double irtF, double uF, double vF, T* bar) {
   using G = Geo<D>;
-  constexpr int Q = D == 2 ? Q1 * Q1 : Q1;
+  constexpr int Q = D == 2 ? Q1 * Q1 : Q1;  // populations of the lattice
+  constexpr int NQ = D == 2 ? Q1 * NK : Q1; // populations of this part
   auto tfs = [&](int slot, T* out) {
+    // compiler-only memory fence: the LDS loads of one stencil cell are not
+    // hoisted above the work of the previous one
+    asm volatile("" ::: "memory");
     const int h = st[slot];
     T in[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
-    transform<D, Q1, T>(sm.RT[h], sm.U[h], D == 2 ? sm.V[h] : 0.0, irtF, uF, vF, in, out);
+    transform_part<D, Q1, T, AXIS, K0, NK>(sm.RT[h], sm.U[h], D == 2 ? sm.V[h] : 0.0, irtF, uF,
+                                           vF, in, out);
     // keep the scheduler from overlapping the stencil cells' transforms
     // (each one holds its own LDS loads and coefficients in registers)
     __builtin_amdgcn_sched_barrier(0);
   };
-  // normal / transverse particle velocities in the face frame (FP64)
-  auto vnorm = [&](int i) {
-    return rtF * node<Q1, double>(AXIS == 0 ? (i % Q1) : (i / Q1)) + (AXIS == 0 ? uF : vF);
-  };
-  auto dtrans = [&](int i) {
-    return T(-0.5 * a.lam * (rtF * node<Q1, double>(AXIS == 0 ? (i / Q1) : (i % Q1)) + (AXIS == 0 ? vF : uF)));
-  };
-  // upwind weights: 1 on the upwind side, 1/2 on both sides at a tie; a
-  // normal velocity within kTieBand of the face thermal speed is a tie, so
-  // rounding noise around a fluid at rest cannot pick a side
+  auto nidx = [](int j) { return j % Q1; };                     // normal node index
+  auto tidx = [](int j) { return D == 2 ? K0 + j / Q1 : 0; };   // transverse node index
+  // upwind side decided in FP64 (bit j: population j upwinded from L / tied)
   const double band = kTieBand * rtF;
-  auto wl = [&](int i) { const double v = vnorm(i); return v > band ? T(1) : (v < -band ? T(0) : T(0.5)); };
-  auto wr = [&](int i) { const double v = vnorm(i); return v < -band ? T(1) : (v > band ? T(0) : T(0.5)); };
-  T PL[Q], PR[Q], rec[Q];
+  unsigned left = 0, tie = 0;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    const double v = rtF * node<Q1, double>(nidx(j)) + (AXIS == 0 ? uF : vF);
+    if (!(v < -band)) left |= 1u << j;
+    if (!(v < -band) && !(v > band)) tie |= 1u << j;
+  }
+  // departure-point offsets in cell units: normal -v_n dt/(2 dx) (+-1/2 from
+  // the upwind centre), transverse -v_t dt/(2 dx)
+  const T rtT = T(rtF), unT = T(AXIS == 0 ? uF : vF), utT = T(AXIS == 0 ? vF : uF);
+  const T hl = T(0.5 * a.lam);
+  auto vnorm = [&](int j) { return rtT * node<Q1, T>(nidx(j)) + unT; };
+  auto dtrans = [&](int j) { return -hl * (rtT * node<Q1, T>(tidx(j)) + utT); };
+  auto isl = [&](int j) { return (left >> j) & 1u; };
+  T PL[NQ], PR[NQ], X[NQ], rec[NQ];
   tfs(0, PL);
   tfs(1, PR);
   {
-    T t[Q];
+    // normal slope: L side limits (PL - P_{L-e}, PR - PL), R side (PR - PL, P_{R+e} - PR)
+    T t[NQ];
     tfs(2, t);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T w = wl(i);
-      rec[i] = w == T(0) ? T(0)
-                         : w * (PL[i] + T(0.5 - 0.5 * a.lam * vnorm(i)) * limit(a.limiter, PL[i] - t[i], PR[i] - PL[i]));
-    }
+    for (int j = 0; j < NQ; ++j) X[j] = PL[j] - t[j];
     tfs(3, t);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T w = wr(i);
-      if (w != T(0))
-        rec[i] += w * (PR[i] + T(-0.5 - 0.5 * a.lam * vnorm(i)) * limit(a.limiter, PR[i] - PL[i], t[i] - PR[i]));
+    for (int j = 0; j < NQ; ++j) {
+      const bool l = isl(j);
+      const T mid = PR[j] - PL[j];
+      const T sa = l ? X[j] : mid, sb = l ? mid : t[j] - PR[j];
+      const T dn = (l ? T(0.5) : T(-0.5)) - hl * vnorm(j);
+      rec[j] = (l ? PL[j] : PR[j]) + dn * limit(a.limiter, sa, sb);
     }
   }
   if constexpr (D == 2) {
-    T tp[Q], tm[Q];
-    tfs(4, tp);
-    tfs(5, tm);
+    // transverse slope at the upwind cell
+    T ta[NQ], tb[NQ];
+    {
+      T t[NQ];
+      tfs(4, t);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T w = wl(i);
-      if (w != T(0)) rec[i] += w * dtrans(i) * limit(a.limiter, PL[i] - tm[i], tp[i] - PL[i]);
-    }
-    tfs(6, tp);
-    tfs(7, tm);
+      for (int j = 0; j < NQ; ++j) tb[j] = t[j] - PL[j];
+      tfs(5, t);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T w = wr(i);
-      if (w != T(0)) rec[i] += w * dtrans(i) * limit(a.limiter, PR[i] - tm[i], tp[i] - PR[i]);
+      for (int j = 0; j < NQ; ++j) ta[j] = PL[j] - t[j];
+      tfs(6, t);
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) tb[j] = isl(j) ? tb[j] : t[j] - PR[j];
+      tfs(7, t);
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) ta[j] = isl(j) ? ta[j] : PR[j] - t[j];
     }
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) rec[j] += dtrans(j) * limit(a.limiter, ta[j], tb[j]);
+  }
+  if (tie) {
+    // ties: the right-upwind reconstruction, then the mean of both
+    T t[NQ], rr[NQ];
+    tfs(3, t);
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+      rr[j] = PR[j] + (T(-0.5) - hl * vnorm(j)) * limit(a.limiter, PR[j] - PL[j], t[j] - PR[j]);
+    if constexpr (D == 2) {
+      T tp[NQ];
+      tfs(6, tp);
+      tfs(7, t);
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) rr[j] += dtrans(j) * limit(a.limiter, PR[j] - t[j], tp[j] - PR[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NQ; ++j)
+      if ((tie >> j) & 1u) rec[j] = T(0.5) * (rec[j] + rr[j]);
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) bar[i] = rec[i];
+  for (int j = 0; j < NQ; ++j) bar[j] = rec[j];
 }
 
 template <int D, typename T, int AXIS>
-__device__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
+__device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG;
   const int hL = st[0], hR = st[1];
   // eq. AvgFrame
   double uF = 0.5 * (sm.U[hL] + sm.U[hR]);
   double vF = D == 2 ? 0.5 * (sm.V[hL] + sm.V[hR]) : 0.0;
-  double TF = 0.5 * (sm.TT[hL] + sm.TT[hR]);
-  T fbar[QF], gbar[QG];
+  double TF = 0.5 * (sm.RT[hL] * sm.RT[hL] + sm.RT[hR] * sm.RT[hR]);
   double rho_b = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0, rtF = 0.0, irtF = 0.0;
+#pragma unroll 1
   for (int pass = 0; pass <= a.n_corr; ++pass) {
     rtF = sqrt(TF);
     irtF = 1.0 / rtF;
-    reconstruct<D, 4, T, AXIS>(a, sm, st, 0, rtF, irtF, uF, vF, fbar);
-    reconstruct<D, 3, T, AXIS>(a, sm, st, QF, rtF, irtF, uF, vF, gbar);
-    // macroscopic fields at the face, in FP64
+    // macroscopic fields at the face, in FP64; f-bar is parked in the face
+    // slot of LDS while g is reconstructed
     double m0 = 0.0, mx = 0.0, my = 0.0, e = 0.0;
-#pragma unroll
-    for (int i = 0; i < QF; ++i) {
-      const double vx = rtF * node<4, double>(i & 3) + uF;
-      const double vy = D == 2 ? rtF * node<4, double>(i >> 2) + vF : 0.0;
-      const double fb = double(fbar[i]);
-      m0 += fb;
-      mx += vx * fb;
-      my += vy * fb;
-      e += 0.5 * (vx * vx + vy * vy) * fb;
+    // f in parts by transverse index (two halves in 2D); g whole
+    auto take_f = [&](const T* bar, int k0, int nk) {
+      for (int j = 0; j < (D == 2 ? 4 * nk : 4); ++j) {
+        const int n = j % 4, t = k0 + j / 4;
+        const int i = D == 1 ? n : (AXIS == 0 ? n + 4 * t : t + 4 * n);
+        const double vx = rtF * node<4, double>(i & 3) + uF;
+        const double vy = D == 2 ? rtF * node<4, double>(i >> 2) + vF : 0.0;
+        const double fb = double(bar[j]);
+        m0 += fb;
+        mx += vx * fb;
+        my += vy * fb;
+        e += 0.5 * (vx * vx + vy * vy) * fb;
+        sm.F[i * G::NF + fidx] = bar[j];
+      }
+    };
+    if constexpr (D == 2) {
+      // one row of the transverse index at a time keeps the reconstruction
+      // within the register budget of two workgroups per CU
+      constexpr int NK = 1;
+      static_for<0, 4 / NK>([&](auto part) {
+        constexpr int K0 = decltype(part)::value * NK;
+        T bar[4 * NK];
+        reconstruct<D, 4, T, AXIS, K0, NK>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+        take_f(bar, K0, NK);
+      });
+    } else {
+      T bar[4];
+      reconstruct<D, 4, T, AXIS, 0, 1>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+      take_f(bar, 0, 1);
     }
+    {
+      constexpr int NKG = 1;
+      static_for<0, (D == 2 ? 3 / NKG : 1)>([&](auto part) {
+        constexpr int K0 = decltype(part)::value * NKG;
+        T gbar[3 * NKG];
+        reconstruct<D, 3, T, AXIS, K0, NKG>(a, sm, st, QF, rtF, irtF, uF, vF, gbar);
 #pragma unroll
-    for (int i = 0; i < QG; ++i) e += double(gbar[i]);
+        for (int j = 0; j < 3 * NKG; ++j) {
+          const int n = j % 3, t = K0 + j / 3;
+          const int i = D == 1 ? n : (AXIS == 0 ? n + 3 * t : t + 3 * n);
+          e += double(gbar[j]);
+          sm.F[(QF + i) * G::NF + fidx] = gbar[j];
+        }
+      });
+    }
     rho_b = m0;
     ub = mx / m0;
     vb = my / m0;
@@ -496,7 +636,8 @@ __device__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo
       TF = Tb;
     }
   }
-  // face equilibrium rho G_{u_b,T_b}^{lambda_F} W (eq. NonComovingEq), separable
+  // face equilibrium rho G_{u_b,T_b}^{lambda_F} W (eq. NonComovingEq), separable;
+  // phi = c1 phi-bar + c2 phi^eq inverts eq. FluxTransf
   const T sb = T(sqrt(Tb) * irtF);
   const T c1 = T(a.c_face1), c2 = T(a.c_face2);
   {
@@ -507,7 +648,8 @@ __device__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
       const T feq = D == 2 ? r * ex[i & 3] * ey[i >> 2] : r * ex[i];
-      fbar[i] = c1 * fbar[i] + c2 * feq;  // phi from phi-bar: inverts eq. FluxTransf
+      T& slot = sm.F[i * G::NF + fidx];
+      slot = c1 * slot + c2 * feq;
     }
   }
   {
@@ -518,17 +660,33 @@ __device__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo
 #pragma unroll
     for (int i = 0; i < QG; ++i) {
       const T geq = D == 2 ? r * ex[i % 3] * ey[i / 3] : r * ex[i];
-      gbar[i] = c1 * gbar[i] + c2 * geq;
+      T& slot = sm.F[(QF + i) * G::NF + fidx];
+      slot = c1 * slot + c2 * geq;
     }
   }
-  // conserved fluxes through the face, in FP64, rounded once to the ledger unit
+  if (!(rho_b > 0.0) || !(Tb > 0.0)) atomicOr(a.flag, 1);
+  sm.FU[fidx] = uF;
+  sm.FV[fidx] = vF;
+  sm.FRT[fidx] = rtF;
+}
+
+// Conserved fluxes through a face (mass, momentum, energy of phi^{lambda_F}
+// times the normal particle velocity in the face frame, App. C), in FP64,
+// times dt/dx and rounded once to the ledger unit.  Both cells next to a face
+// evaluate it from the same LDS data, so they apply the same integer.
+template <int D, typename T, int AXIS>
+__device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& sm, int fi,
+                                          long long (&psi)[4]) {
+  using G = Geo<D>;
+  constexpr int QF = G::QF, QG = G::QG;
+  const double rtF = sm.FRT[fi], uF = sm.FU[fi], vF = sm.FV[fi];
   double Fr = 0.0, Fx = 0.0, Fy = 0.0, FE = 0.0;
 #pragma unroll
   for (int i = 0; i < QF; ++i) {
     const double vx = rtF * node<4, double>(i & 3) + uF;
     const double vy = D == 2 ? rtF * node<4, double>(i >> 2) + vF : 0.0;
     const double vn = AXIS == 0 ? vx : vy;
-    const double p = double(fbar[i]) * vn;
+    const double p = double(sm.F[i * G::NF + fi]) * vn;
     Fr += p;
     Fx += vx * p;
     Fy += vy * p;
@@ -538,22 +696,15 @@ __device__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo
   for (int i = 0; i < QG; ++i) {
     const int in_ = AXIS == 0 ? (i % 3) : (i / 3);
     const double vn = rtF * node<3, double>(in_) + (AXIS == 0 ? uF : vF);
-    FE += vn * double(gbar[i]);
+    FE += vn * double(sm.F[(QF + i) * G::NF + fi]);
   }
   int bad = 0;
   const double sc = a.lam * a.scale;
-  sm.Psi[0 * G::NF + fidx] = to_fixed(Fr, sc, &bad);
-  sm.Psi[1 * G::NF + fidx] = to_fixed(Fx, sc, &bad);
-  sm.Psi[2 * G::NF + fidx] = to_fixed(Fy, sc, &bad);
-  sm.Psi[3 * G::NF + fidx] = to_fixed(FE, sc, &bad);
-  if (bad || !(rho_b > 0.0) || !(Tb > 0.0)) atomicOr(a.flag, bad ? 2 : 1);
-#pragma unroll
-  for (int i = 0; i < QF; ++i) sm.F[i * G::NF + fidx] = fbar[i];
-#pragma unroll
-  for (int i = 0; i < QG; ++i) sm.F[(QF + i) * G::NF + fidx] = gbar[i];
-  sm.FU[fidx] = uF;
-  sm.FV[fidx] = vF;
-  sm.FRT[fidx] = rtF;
+  psi[0] = to_fixed(Fr, sc, &bad);
+  psi[1] = to_fixed(Fx, sc, &bad);
+  psi[2] = to_fixed(Fy, sc, &bad);
+  psi[3] = to_fixed(FE, sc, &bad);
+  if (bad) atomicOr(a.flag, 2);
 }
 
 // Flux of two opposite faces into the cell frame (eq. fluxEq):
@@ -574,12 +725,14 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
     transform<D, 4, T>(rtF, uF, vF, c.irt, c.ux, c.uy, in, out);
 #pragma unroll
     for (int i = 0; i < QF; ++i) dlt[i] = side ? out[i] - dlt[i] : out[i];
+    __builtin_amdgcn_sched_barrier(0);
     T ing[QG], outg[QG];
 #pragma unroll
     for (int i = 0; i < QG; ++i) ing[i] = sm.F[(QF + i) * G::NF + fi];
     transform<D, 3, T>(rtF, uF, vF, c.irt, c.ux, c.uy, ing, outg);
 #pragma unroll
     for (int i = 0; i < QG; ++i) dlt[QF + i] = side ? outg[i] - dlt[QF + i] : outg[i];
+    __builtin_amdgcn_sched_barrier(0);
   }
   const T rt = T(c.rt), u = T(AXIS == 0 ? c.ux : c.uy);
 #pragma unroll
@@ -598,7 +751,7 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
 // The fused step kernel.
 // --------------------------------------------------------------------------
 template <int D, typename T>
-__global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
+__global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) step_kernel(StepArgs a) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
   __shared__ Smem<D, T> sm;
@@ -608,6 +761,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   const T kappa = T(a.kappa), apre = T(a.a_pre);
 
   // ---- 0. halo tile: ghost resolution, frame, first QE half step, phi-bar-plus
+#pragma unroll 1
   for (int k = tid; k < G::NH; k += kThreads) {
     int hx, hy;
     slot_coords<D>(k, &hx, &hy);
@@ -625,7 +779,6 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     for (int i = 0; i < QG; ++i) sm.P[(QF + i) * G::NH + h] = rg * wg<D, T>(i) + apre * n[QF + i];
     sm.U[h] = fr.ux;
     sm.V[h] = fr.uy;
-    sm.TT[h] = fr.T;
     sm.RT[h] = fr.rt;
   }
   __syncthreads();
@@ -637,7 +790,7 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     const int h = cx + 2 + G::HX * (cy + G::OY);
     ownF.ux = sm.U[h];
     ownF.uy = sm.V[h];
-    ownF.T = sm.TT[h];
+    ownF.T = sm.RT[h] * sm.RT[h];
     ownF.rt = sm.RT[h];
     ownF.irt = 1.0 / ownF.rt;
   }
@@ -670,10 +823,23 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
   if (tid < G::NI) {
     const int fw = cx + (G::TX + 1) * cy;
     gather_faces<D, T, 0>(sm, fw, fw + 1, ownF, acc);
+    long long pw[4], pe[4];
+    __builtin_amdgcn_sched_barrier(0);
+    face_flux<D, T, 0>(a, sm, fw, pw);
+    __builtin_amdgcn_sched_barrier(0);
+    face_flux<D, T, 0>(a, sm, fw + 1, pe);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dU[q] += sm.Psi[q * G::NF + fw + 1] - sm.Psi[q * G::NF + fw];
+    for (int q = 0; q < 4; ++q) dU[q] += pe[q] - pw[q];
   }
   if constexpr (D == 2) {
+    // park the x-flux in the cell's own output slot (written only by this
+    // thread, read by nobody else this step) while the y-faces use the registers
+    T* nout = static_cast<T*>(a.n_out);
+    const size_t ocell = size_t(x0 + cx) + size_t(a.nx) * size_t(y0 + cy);
+    if (own_in) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) nout[i * a.cells + ocell] = acc[i];
+    }
     __syncthreads();
     // ---- 3. y-faces
     if (tid < G::NFY) {
@@ -692,11 +858,20 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     }
     __syncthreads();
     // ---- 4. south/north faces
+    if (own_in) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) acc[i] = nout[i * a.cells + ocell];
+    }
     if (tid < G::NI) {
       const int fs = cx + G::TX * cy;
       gather_faces<D, T, 1>(sm, fs, fs + G::TX, ownF, acc);
+      long long ps[4], pn[4];
+      __builtin_amdgcn_sched_barrier(0);
+      face_flux<D, T, 1>(a, sm, fs, ps);
+      __builtin_amdgcn_sched_barrier(0);
+      face_flux<D, T, 1>(a, sm, fs + G::TX, pn);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) dU[q] += sm.Psi[q * G::NF + fs + G::TX] - sm.Psi[q * G::NF + fs];
+      for (int q = 0; q < 4; ++q) dU[q] += pn[q] - ps[q];
     }
   }
 
@@ -719,8 +894,11 @@ __global__ void __launch_bounds__(kThreads) step_kernel(StepArgs a) {
     for (int q = 0; q < 4; ++q) U2[q] = U[q] - dU[q];
     const Frame nf = gauge(U2, a);
     T n2[NP];
+    __builtin_amdgcn_sched_barrier(0);
     transform<D, 4, T>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
+    __builtin_amdgcn_sched_barrier(0);
     transform<D, 3, T>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, gt, n2 + QF);
+    __builtin_amdgcn_sched_barrier(0);
     const T r2 = T(nf.rho), rg2 = T(a.geq * nf.T * nf.rho);
 #pragma unroll
     for (int i = 0; i < QF; ++i) n2[i] -= r2 * wf<D, T>(i);

@@ -38,6 +38,7 @@ struct pond_state {
   void* n[2] = {nullptr, nullptr};        // non-equilibrium population planes (ping-pong)
   long long* U[2] = {nullptr, nullptr};   // conserved-moment ledger planes (ping-pong)
   int* flag = nullptr;
+  long long* inflow_dev = nullptr;        // [4][4] fixed-point moments of the inflow states
   long long* red = nullptr;
   double* stage = nullptr;
   int cur = 0;
