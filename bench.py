@@ -60,6 +60,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--serving-requests", type=int, default=64,
+                   help="requests of the serving leg (0 skips it)")
+    p.add_argument("--serving-sizes", type=str, default="128,256,512",
+                   help="grid sides drawn uniformly by the serving leg")
+    p.add_argument("--serving-arena-gb", type=float, default=16.0)
+    p.add_argument("--serving-max-active", type=int, default=64)
     p.add_argument("--copy-mb", type=int, default=0,
                    help="after timing, copy this many MiB device-to-device (counter calibration)")
     return p.parse_args()
@@ -114,6 +120,53 @@ def cpu_baseline(wl_full, seconds):
                       f"{steps} FP64 steps in {el:.1f} s"}
 
 
+def serving_leg(n_req, sizes, arena_gb, max_active):
+    """Poisson stream of independent mixed-precision solves (rate 50/s, seed 5)
+    through the serving loop: submit at each arrival time, poll until done.
+    Latency = t_done - t_submit on the server's clock."""
+    import numpy as np
+    import torch
+    from paper_2302_00310_amd import inputs, pond
+    reqs = inputs.serving_requests(n_req, sizes=sizes)
+    arena_bytes = int(arena_gb * (1 << 30))
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = pond.pond_server_create(arena.data_ptr(), arena_bytes, 0, max_active)
+    ids, results = [], {}
+    cells_steps = 0
+    t0 = time.perf_counter()
+    k = 0
+    try:
+        while len(results) < len(reqs):
+            now = time.perf_counter() - t0
+            while k < len(reqs) and reqs[k].arrival <= now:
+                wl = reqs[k].workload
+                cfg = pond.make_config(wl, precision=pond.POND_MIXED)
+                ids.append(pond.pond_submit(srv, cfg, *wl.fields(), wl.steps, tag=k))
+                cells_steps += wl.nx * wl.ny * wl.steps
+                k += 1
+            for j, rid in enumerate(ids):
+                if j in results:
+                    continue
+                wl = reqs[j].workload
+                rc, _, times = pond.pond_poll(srv, rid, wl.nx * wl.ny)
+                if rc != pond.POND_PENDING:
+                    results[j] = (rc, times)
+            time.sleep(0.001)
+        makespan = time.perf_counter() - t0
+    finally:
+        pond.pond_server_destroy(srv)
+    lat = np.array([r[1]["t_done"] - r[1]["t_submit"] for r in results.values()])
+    queue = np.array([r[1]["t_admit"] - r[1]["t_submit"] for r in results.values()])
+    serv = np.array([r[1]["t_done"] - r[1]["t_admit"] for r in results.values()])
+    return {"requests": len(reqs), "ok": int(sum(1 for r in results.values() if r[0] == 0)),
+            "sizes": list(sizes), "rate_per_s": 50.0, "arena_gb": arena_gb,
+            "max_active": max_active, "policy": "FCFS with memory admission",
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "queue_p50_s": float(np.percentile(queue, 50)), "queue_p99_s": float(np.percentile(queue, 99)),
+            "service_p50_s": float(np.percentile(serv, 50)), "service_p99_s": float(np.percentile(serv, 99)),
+            "throughput_cell_updates_per_s": cells_steps / makespan, "makespan_s": makespan}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -142,7 +195,7 @@ def main():
     achieved_tf = flops * cells / (kern_m * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
-                       "traffic": None, "kernel": "step_kernel<2,float>",
+                       "traffic": None, "kernel": "step_batch_kernel<2,float>",
                        "kernel_ms": kern_m, "flops_per_cell": flops}
     hbm = BYTES_PER_CELL["mixed"] * cells / (kern_m * 1e-3) / 1e9
     out["hbm_roofline"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -155,6 +208,10 @@ def main():
                        "hbm_frac": BYTES_PER_CELL["fp64"] * cells / (kern_d * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "alu_frac": flops * cells / (kern_d * 1e-3) / 1e12 / VALU_PEAK_TFLOPS}
         out["mixed_over_fp64"] = value / v64
+    if a.serving_requests > 0:
+        sizes = tuple(int(v) for v in a.serving_sizes.split(","))
+        out["serving"] = serving_leg(a.serving_requests, sizes, a.serving_arena_gb,
+                                     a.serving_max_active)
     if a.copy_mb:
         x = torch.empty(a.copy_mb << 20, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)

@@ -88,7 +88,8 @@ Layout layout_of(const pond_config* c) {
   L.stage_rows = size_t(std::max(4, L.NP + 3));
   L.stage_cells = std::min(L.cells, size_t(kStagingBytes / (8 * L.stage_rows)));
   L.stage_bytes = align256(L.stage_rows * L.stage_cells * 8);
-  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.red_bytes + L.stage_bytes;
+  L.tab_bytes = align256(sizeof(BatchEntry));
+  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.tab_bytes + L.red_bytes + L.stage_bytes;
   return L;
 }
 
@@ -126,6 +127,26 @@ static int sync_flag(pond_state* s) {
   POND_HIP(hipMemcpy(&flag, s->flag, sizeof(int), hipMemcpyDeviceToHost));
   if (flag & 2) return fail(POND_ERR_UNSTABLE, "conserved-moment ledger overflow");
   if (flag & 1) return fail(POND_ERR_UNSTABLE, "non-physical state (rho <= 0, T <= 0 or non-finite)");
+  return POND_OK;
+}
+
+// The 2D step runs the batched kernel with a one-entry table (the same
+// machine code as a solve inside the serving batch, so results agree bit for
+// bit): entry.args[p] advances buffer p to buffer 1 - p.
+int upload_table(pond_state* s) {
+  if (s->cfg.dim != 2) return POND_OK;
+  BatchEntry e{};
+  for (int par = 0; par < 2; ++par) {
+    e.args[par] = s->args;
+    e.args[par].n_in = s->n[par];
+    e.args[par].n_out = s->n[1 - par];
+    e.args[par].U_in = s->U[par];
+    e.args[par].U_out = s->U[1 - par];
+  }
+  e.tile_begin = 0;
+  e.tiles = s->args.tiles_x * s->args.tiles_y;
+  POND_HIP(hipMemcpyAsync(s->tab, &e, sizeof e, hipMemcpyHostToDevice, s->stream));
+  POND_HIP(hipStreamSynchronize(s->stream));
   return POND_OK;
 }
 
@@ -172,6 +193,7 @@ int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, voi
   s->U[1] = reinterpret_cast<long long*>(p); p += L.led_bytes;
   s->flag = reinterpret_cast<int*>(p); p += 256;
   s->inflow_dev = reinterpret_cast<long long*>(p); p += 256;
+  s->tab = reinterpret_cast<BatchEntry*>(p); p += L.tab_bytes;
   s->red = reinterpret_cast<long long*>(p); p += L.red_bytes;
   s->stage = reinterpret_cast<double*>(p);
   s->dx = cfg->dx > 0.0 ? cfg->dx : 1.0 / cfg->nx;
@@ -281,19 +303,24 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   a.inflow = s->inflow_dev;
   a.cells = n;
   a.flag = s->flag;
-  return POND_OK;
+  return upload_table(s);
 }
 
 int pond_step(pond_state* s, int nsteps) {
   if (!s || nsteps < 0) return fail(POND_ERR_INVALID, "bad arguments");
   if (!s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
   for (int k = 0; k < nsteps; ++k) {
-    StepArgs a = s->args;
-    a.n_in = s->n[s->cur];
-    a.n_out = s->n[1 - s->cur];
-    a.U_in = s->U[s->cur];
-    a.U_out = s->U[1 - s->cur];
-    POND_HIP(launch_step(s->cfg.dim, s->L.fp64, a, s->stream));
+    if (s->cfg.dim == 2) {
+      POND_HIP(launch_step_batch(s->L.fp64, s->tab, 1, s->args.tiles_x * s->args.tiles_y, s->cur,
+                                 s->stream));
+    } else {
+      StepArgs a = s->args;
+      a.n_in = s->n[s->cur];
+      a.n_out = s->n[1 - s->cur];
+      a.U_in = s->U[s->cur];
+      a.U_out = s->U[1 - s->cur];
+      POND_HIP(launch_step_1d(s->L.fp64, a, s->stream));
+    }
     s->cur ^= 1;
     s->nstep++;
   }
@@ -464,7 +491,7 @@ int pond_load(pond_state* s, const char* path) {
   s->cur = 0;
   POND_HIP(hipMemcpy(s->n[0], buf.data(), h.pop_bytes, hipMemcpyHostToDevice));
   POND_HIP(hipMemcpy(s->U[0], buf.data() + h.pop_bytes, h.led_bytes, hipMemcpyHostToDevice));
-  return POND_OK;
+  return upload_table(s);
 }
 
 int pond_destroy(pond_state* s) {

@@ -50,8 +50,18 @@ struct StepArgs {
   int* flag;               // bit 1: non-physical state, bit 2: ledger overflow
 };
 
+// One solve of a batched step launch: the arguments of its even and odd
+// steps (ping-pong buffers swapped) and the first block of its tile range.
+struct BatchEntry {
+  StepArgs args[2];
+  int tile_begin;
+  int tiles;
+};
+
 // Host-side launchers (defined in pond_kernels.hip).
-hipError_t launch_step(int dim, bool fp64, const StepArgs& a, hipStream_t st);
+hipError_t launch_step_batch(bool fp64, const BatchEntry* tab, int n, int total_tiles, int parity,
+                             hipStream_t st);
+hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
 hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,
                        size_t count, double scale, double cv, void* n, long long* U,
                        hipStream_t st);

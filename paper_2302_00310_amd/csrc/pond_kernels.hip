@@ -751,12 +751,11 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
 // The fused step kernel.
 // --------------------------------------------------------------------------
 template <int D, typename T>
-__global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
-  __shared__ Smem<D, T> sm;
   const int tid = threadIdx.x;
-  const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
+  const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
   const int x0 = bx * G::TX, y0 = by * G::TY;
   const T kappa = T(a.kappa), apre = T(a.a_pre);
 
@@ -919,6 +918,30 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) 
   }
 }
 
+// One 1D solve: block b advances tile b.
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) step_kernel(StepArgs a) {
+  __shared__ Smem<D, T> sm;
+  step_tile<D, T>(a, blockIdx.x, sm);
+}
+
+// A ragged batch of independent solves in one launch: block b advances tile
+// b - tile_begin of the entry whose tile range holds b.  Each entry carries
+// the arguments of both step parities; step `parity` uses args[parity].
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
+    step_batch_kernel(const BatchEntry* tab, int n, int parity) {
+  __shared__ Smem<D, T> sm;
+  int lo = 0, hi = n - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {  // last entry with tile_begin <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].tile_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const BatchEntry& e = tab[lo];
+  step_tile<D, T>(e.args[parity], b - e.tile_begin, sm);
+}
+
 // --------------------------------------------------------------------------
 // Initial data, observables, exact totals.
 // --------------------------------------------------------------------------
@@ -1006,15 +1029,18 @@ __global__ void __launch_bounds__(256) totals_kernel(const long long* U, size_t 
 
 }  // namespace
 
-hipError_t launch_step(int dim, bool fp64, const StepArgs& a, hipStream_t st) {
+hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st) {
   const dim3 grid(a.tiles_x * a.tiles_y), block(kThreads);
-  if (dim == 1) {
-    if (fp64) hipLaunchKernelGGL((step_kernel<1, double>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((step_kernel<1, float>), grid, block, 0, st, a);
-  } else {
-    if (fp64) hipLaunchKernelGGL((step_kernel<2, double>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((step_kernel<2, float>), grid, block, 0, st, a);
-  }
+  if (fp64) hipLaunchKernelGGL((step_kernel<1, double>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((step_kernel<1, float>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_batch(bool fp64, const BatchEntry* tab, int n, int total_tiles, int parity,
+                             hipStream_t st) {
+  const dim3 grid(total_tiles), block(kThreads);
+  if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double>), grid, block, 0, st, tab, n, parity);
+  else hipLaunchKernelGGL((step_batch_kernel<2, float>), grid, block, 0, st, tab, n, parity);
   return hipGetLastError();
 }
 

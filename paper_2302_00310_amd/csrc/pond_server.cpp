@@ -1,23 +1,409 @@
-// Serving loop of libpond.so (continuous batching of independent solves).
+// Serving loop of libpond.so: continuous batching of independent 2D solves.
+//
+// A server thread owns a device arena and a stream.  Requests are queued by
+// pond_submit (host copies of their inputs, no GPU work) and admitted first
+// come, first served as soon as their footprint fits a first-fit free list
+// over the arena and a batch slot is free.  Every iteration advances all
+// resident solves together by K steps: one batched step kernel per step
+// covers the tiles of all of them (a device table maps blocks to solves), and
+// the K launches are captured once per change of the resident set into a
+// HIP graph that is replayed while the set is unchanged.  Solves that reach
+// their step count are retired: moments copied to host, status recorded
+// (a non-physical state fails that solve only), arena released.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "../../include/pond.h"
+#include "pond_internal.h"
 #include "pond_state.h"
 
 using namespace pond;
 
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr int kChunk = 16;  // steps per iteration (fewer when a solve finishes earlier)
+
+struct Job {
+  uint64_t id = 0, tag = 0;
+  pond_config cfg{};
+  std::vector<double> rho, ux, uy, p;
+  int nsteps = 0, remaining = 0;
+  int status = POND_PENDING;
+  double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
+  size_t off = 0, bytes = 0;
+  pond_state* st = nullptr;
+  std::vector<double> out;  // rho, ux, uy, T planes after completion
+};
+
+// First-fit free list over [0, size), 256-byte granules.
+class FreeList {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool take(size_t n, size_t* off) {
+    n = (n + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const size_t rest = it->second - n, at = it->first + n;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+}  // namespace
+
+struct pond_server {
+  char* arena = nullptr;
+  size_t bytes = 0, usable = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int max_active = 0;
+  BatchEntry* dev_tab = nullptr;
+  BatchEntry* host_tab = nullptr;  // pinned
+  FreeList alloc;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Job*> queue;
+  std::vector<Job*> active;
+  std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::thread th;
+  std::atomic<bool> stop{false};
+  uint64_t next_id = 1;
+  Clock::time_point t0;
+  // graph cache for the current resident set: key = (K, parity of the first step)
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  int n_tab = 0, total_tiles = 0, phase = 0;
+  int device = 0;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+void drop_graphs(pond_server* S) {
+  for (auto& kv : S->graphs) hipGraphExecDestroy(kv.second);
+  S->graphs.clear();
+}
+
+int tiles_of(const pond_config& c) {
+  return ((c.nx + kTX2 - 1) / kTX2) * ((c.ny + kTY2 - 1) / kTY2);
+}
+
+// Rebuild the device table of resident solves.
+int upload_table(pond_server* S) {
+  drop_graphs(S);
+  int tile = 0;
+  for (size_t k = 0; k < S->active.size(); ++k) {
+    pond_state* s = S->active[k]->st;
+    BatchEntry& e = S->host_tab[k];
+    for (int par = 0; par < 2; ++par) {
+      const int in = par ? 1 - s->cur : s->cur;
+      e.args[par] = s->args;
+      e.args[par].n_in = s->n[in];
+      e.args[par].n_out = s->n[1 - in];
+      e.args[par].U_in = s->U[in];
+      e.args[par].U_out = s->U[1 - in];
+    }
+    e.tile_begin = tile;
+    e.tiles = tiles_of(s->cfg);
+    tile += e.tiles;
+  }
+  S->n_tab = int(S->active.size());
+  S->total_tiles = tile;
+  S->phase = 0;
+  hipError_t err = hipMemcpyAsync(S->dev_tab, S->host_tab, sizeof(BatchEntry) * S->n_tab,
+                                  hipMemcpyHostToDevice, S->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(S->stream);
+  return err == hipSuccess ? POND_OK : hip_fail(err, "batch table upload");
+}
+
+// K batched steps, captured into a graph on first use for this resident set.
+int run_steps(pond_server* S, int K) {
+  const int par0 = S->phase & 1;
+  auto key = std::make_pair(K, par0);
+  auto it = S->graphs.find(key);
+  if (it == S->graphs.end()) {
+    hipError_t err = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
+    for (int j = 0; j < K; ++j)
+      launch_step_batch(false, S->dev_tab, S->n_tab, S->total_tiles, (par0 + j) & 1, S->stream);
+    hipGraph_t g = nullptr;
+    err = hipStreamEndCapture(S->stream, &g);
+    if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (err != hipSuccess) return hip_fail(err, "hipGraphInstantiate");
+    it = S->graphs.emplace(key, ex).first;
+  }
+  hipError_t err = hipGraphLaunch(it->second, S->stream);
+  if (err != hipSuccess) return hip_fail(err, "hipGraphLaunch");
+  S->phase += K;
+  for (Job* j : S->active) {
+    j->remaining -= K;
+    j->st->cur ^= (K & 1);
+    j->st->nstep += K;
+  }
+  return POND_OK;
+}
+
+void finish(pond_server* S, Job* j, int status) {
+  if (j->st) {
+    pond_destroy(j->st);
+    j->st = nullptr;
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  j->t_done = S->now();
+  j->status = status;  // published under the lock: pond_poll reads it there
+  S->alloc.give(j->off, j->bytes);
+  S->cv.notify_all();
+}
+
+void serve(pond_server* S) {
+  hipSetDevice(S->device);
+  std::vector<Job*> admit;
+  bool changed = false;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      while (!S->stop && !S->queue.empty() &&
+             int(S->active.size() + admit.size()) < S->max_active) {
+        Job* j = S->queue.front();
+        size_t off = 0;
+        if (!S->alloc.take(j->bytes, &off)) break;  // first come, first served: wait for memory
+        j->off = off;
+        S->queue.pop_front();
+        admit.push_back(j);
+      }
+      if (S->active.empty() && admit.empty()) {
+        if (S->stop) break;
+        S->cv.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+    }
+    // admission: state in the job's arena region, comoving equilibrium on device
+    for (Job* j : admit) {
+      pond_state* st = nullptr;
+      int rc = pond_create(&j->cfg, S->arena + j->off, j->bytes, S->stream, &st);
+      if (rc == POND_OK)
+        rc = pond_init_fields(st, j->rho.data(), j->ux.data(), j->uy.data(), j->p.data());
+      j->st = st;
+      std::vector<double>().swap(j->rho);
+      std::vector<double>().swap(j->ux);
+      std::vector<double>().swap(j->uy);
+      std::vector<double>().swap(j->p);
+      if (rc != POND_OK) {
+        finish(S, j, rc);
+        continue;
+      }
+      j->t_admit = S->now();
+      j->remaining = j->nsteps;
+      if (j->remaining == 0) {
+        j->out.assign(4 * size_t(j->cfg.nx) * j->cfg.ny, 0.0);
+        const size_t n = size_t(j->cfg.nx) * j->cfg.ny;
+        const int mrc = pond_moments(st, j->out.data(), j->out.data() + n, j->out.data() + 2 * n,
+                                     j->out.data() + 3 * n);
+        finish(S, j, mrc);
+        continue;
+      }
+      S->active.push_back(j);
+      changed = true;
+    }
+    admit.clear();
+    if (S->active.empty()) continue;
+    if (changed) {
+      if (upload_table(S) != POND_OK) {
+        for (Job* j : S->active) finish(S, j, POND_ERR_DEVICE);
+        S->active.clear();
+        continue;
+      }
+      changed = false;
+    }
+    int K = kChunk;
+    for (Job* j : S->active) K = std::min(K, j->remaining);
+    if (run_steps(S, K) != POND_OK) {
+      for (Job* j : S->active) finish(S, j, POND_ERR_DEVICE);
+      S->active.clear();
+      changed = true;
+      continue;
+    }
+    // retire the solves that reached their step count
+    bool any = false;
+    for (Job* j : S->active) any |= j->remaining == 0;
+    if (!any) continue;
+    std::vector<Job*> keep;
+    for (Job* j : S->active) {
+      if (j->remaining > 0) {
+        keep.push_back(j);
+        continue;
+      }
+      const size_t n = size_t(j->cfg.nx) * j->cfg.ny;
+      j->out.assign(4 * n, 0.0);
+      const int rc = pond_moments(j->st, j->out.data(), j->out.data() + n, j->out.data() + 2 * n,
+                                  j->out.data() + 3 * n);
+      finish(S, j, rc);
+    }
+    S->active.swap(keep);
+    changed = true;
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
-int pond_server_create(void*, size_t, void*, int, pond_server** out) {
-  if (out) *out = nullptr;
-  return fail(POND_ERR_UNSUPPORTED, "serving is not built yet");
+int pond_server_create(void* dev_arena, size_t bytes, void* hip_stream, int max_active,
+                       pond_server** out) {
+  if (!out) return fail(POND_ERR_INVALID, "null output handle");
+  *out = nullptr;
+  if (max_active < 1 || max_active > 4096) return fail(POND_ERR_INVALID, "max_active must lie in 1..4096");
+  if (!dev_arena || (reinterpret_cast<uintptr_t>(dev_arena) & 255))
+    return fail(POND_ERR_INVALID, "arena must be a 256-byte aligned device pointer");
+  const size_t tab = (sizeof(BatchEntry) * size_t(max_active) + 255) & ~size_t(255);
+  if (bytes <= tab) return fail(POND_ERR_NOMEM, "arena smaller than the batch table");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::unique_ptr<pond_server> S(new pond_server());
+  S->device = dev;
+  S->arena = static_cast<char*>(dev_arena) + tab;
+  S->bytes = bytes;
+  S->usable = bytes - tab;
+  S->dev_tab = static_cast<BatchEntry*>(dev_arena);
+  S->max_active = max_active;
+  // graph capture needs a stream other than the legacy default one
+  if (hip_stream) {
+    S->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    S->own_stream = true;
+  }
+  e = hipHostMalloc(reinterpret_cast<void**>(&S->host_tab), sizeof(BatchEntry) * size_t(max_active));
+  if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+  S->alloc.reset(S->usable);
+  S->t0 = Clock::now();
+  pond_server* raw = S.release();
+  raw->th = std::thread(serve, raw);
+  *out = raw;
+  return POND_OK;
 }
-int pond_submit(pond_server*, const pond_request*, uint64_t*) {
-  return fail(POND_ERR_UNSUPPORTED, "serving is not built yet");
+
+int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
+  if (!S || !req || !id) return fail(POND_ERR_INVALID, "null argument");
+  const pond_config& c = req->cfg;
+  int rc = validate(&c);
+  if (rc) return rc;
+  if (c.dim != 2) return fail(POND_ERR_UNSUPPORTED, "serving runs 2D solves");
+  if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
+  if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
+  if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");
+  const size_t need = layout_of(&c).total;
+  if (need > S->usable) return fail(POND_ERR_REJECTED, "solve footprint exceeds the whole arena");
+  const size_t n = size_t(c.nx) * c.ny;
+  std::unique_ptr<Job> j(new Job());
+  j->cfg = c;
+  j->tag = req->tag;
+  j->nsteps = req->nsteps;
+  j->bytes = need;
+  j->rho.assign(req->rho, req->rho + n);
+  j->ux.assign(req->ux, req->ux + n);
+  j->uy.assign(req->uy, req->uy + n);
+  j->p.assign(req->p, req->p + n);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) return fail(POND_ERR_INVALID, "server is stopping");
+  j->id = S->next_id++;
+  j->t_submit = S->now();
+  *id = j->id;
+  S->queue.push_back(j.get());
+  S->jobs.emplace(j->id, std::move(j));
+  S->cv.notify_all();
+  return POND_OK;
 }
-int pond_poll(pond_server*, uint64_t, pond_result*) {
-  return fail(POND_ERR_UNSUPPORTED, "serving is not built yet");
+
+int pond_poll(pond_server* S, uint64_t id, pond_result* res) {
+  if (!S || !res) return fail(POND_ERR_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(id);
+  if (it == S->jobs.end()) return fail(POND_ERR_INVALID, "unknown request id");
+  Job* j = it->second.get();
+  if (j->status == POND_PENDING) return POND_PENDING;
+  res->status = j->status;
+  res->t_submit = j->t_submit;
+  res->t_admit = j->t_admit;
+  res->t_done = j->t_done;
+  res->tag = j->tag;
+  const size_t n = size_t(j->cfg.nx) * j->cfg.ny;
+  if (j->out.size() == 4 * n) {
+    double* dst[4] = {res->rho, res->ux, res->uy, res->T};
+    for (int q = 0; q < 4; ++q)
+      if (dst[q]) std::memcpy(dst[q], j->out.data() + q * n, n * sizeof(double));
+  }
+  const int status = j->status;
+  S->jobs.erase(it);
+  return status;
 }
-int pond_server_destroy(pond_server*) { return POND_OK; }
+
+int pond_server_destroy(pond_server* S) {
+  if (!S) return POND_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    // queued work is dropped; resident solves finish
+    for (Job* j : S->queue) {
+      j->status = POND_ERR_INVALID;
+      j->t_done = S->now();
+    }
+    S->queue.clear();
+    S->cv.notify_all();
+  }
+  if (S->th.joinable()) S->th.join();
+  drop_graphs(S);
+  if (S->host_tab) hipHostFree(S->host_tab);
+  hipStreamSynchronize(S->stream);
+  if (S->own_stream) hipStreamDestroy(S->stream);
+  delete S;
+  return POND_OK;
+}
 
 }  // extern "C"

@@ -18,7 +18,7 @@ struct Layout {
   int D = 2, QF = 16, QG = 9, NP = 25;
   bool fp64 = false;
   size_t cells = 0;
-  size_t pop_bytes = 0, led_bytes = 0, red_bytes = 0, stage_bytes = 0;
+  size_t pop_bytes = 0, led_bytes = 0, red_bytes = 0, stage_bytes = 0, tab_bytes = 0;
   size_t stage_rows = 0, stage_cells = 0;
   int red_blocks = 256;
   size_t total = 0;
@@ -27,6 +27,7 @@ struct Layout {
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 int validate(const pond_config* c);
+int upload_table(pond_state* s);
 Layout layout_of(const pond_config* c);
 
 }  // namespace pond
@@ -39,6 +40,7 @@ struct pond_state {
   long long* U[2] = {nullptr, nullptr};   // conserved-moment ledger planes (ping-pong)
   int* flag = nullptr;
   long long* inflow_dev = nullptr;        // [4][4] fixed-point moments of the inflow states
+  pond::BatchEntry* tab = nullptr;        // one-entry step table (2D): the kernel serving uses
   long long* red = nullptr;
   double* stage = nullptr;
   int cur = 0;

@@ -268,3 +268,41 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---- serving ----------------------------------------------------------------
+def pond_server_create(dev_arena: int, arena_bytes: int, hip_stream: int, max_active: int):
+    h = C.c_void_p()
+    check(load_library().pond_server_create(C.c_void_p(dev_arena), arena_bytes,
+                                            C.c_void_p(hip_stream), int(max_active), C.byref(h)))
+    return h
+
+
+def pond_submit(srv, cfg: pond_config, rho, ux, uy, p, nsteps: int, tag: int = 0) -> int:
+    req = pond_request()
+    req.cfg = cfg
+    arrs = [_host(a) for a in (rho, ux, uy, p)]
+    req.rho, req.ux, req.uy, req.p = (_ptr(a) for a in arrs)
+    req.nsteps = int(nsteps)
+    req.tag = int(tag)
+    rid = C.c_uint64()
+    check(load_library().pond_submit(srv, C.byref(req), C.byref(rid)))
+    return rid.value
+
+
+def pond_poll(srv, rid: int, n: int):
+    """(status, (rho, ux, uy, T) or None, times dict or None); status 1 = pending."""
+    res = pond_result()
+    out = [np.empty(n) for _ in range(4)]
+    res.rho, res.ux, res.uy, res.T = (_ptr(a) for a in out)
+    rc = load_library().pond_poll(srv, C.c_uint64(rid), C.byref(res))
+    if rc == POND_PENDING:
+        return rc, None, None
+    if rc < 0 and res.t_submit == 0.0 and res.t_done == 0.0:
+        raise PondError(rc, last_error())
+    times = {"t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done, "tag": res.tag}
+    return rc, out, times
+
+
+def pond_server_destroy(srv):
+    return check(load_library().pond_server_destroy(srv))

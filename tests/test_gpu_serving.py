@@ -1,0 +1,125 @@
+"""Serving: continuous batching of independent solves (pond_server_* through the
+C interface).  Each result must be the same alone and in the mix; admission
+waits for arena memory; an oversize request is rejected at submit; a solve
+that goes non-physical fails alone."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2302_00310_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pond():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2302_00310_amd import pond as p
+    p.load_library()
+    return p
+
+
+def _mix():
+    return [
+        (inputs.vortex_2d(48, steps=1, mach=1.5, noise=1e-3, seed=21, prandtl=0.6, tau=0.6, ny=40), 37),
+        (inputs.quadrants_2d(64, steps=1, seed=22, prandtl=0.9, tau=0.52), 50),
+        (inputs.quadrants_2d(33, steps=1, seed=23, prandtl=0.71, tau=0.7, ny=47), 20),
+        (inputs.vortex_2d(96, steps=1, mach=3.0, noise=1e-3, seed=24, prandtl=1.0, tau=0.55), 64),
+        (inputs.quadrants_2d(128, steps=1, seed=25, prandtl=0.5, tau=0.51, ny=64), 45),
+    ]
+
+
+def _alone(pond, wl, steps):
+    s = pond.Solver(wl, precision=pond.POND_MIXED)
+    s.step(steps)
+    m = s.moments()
+    s.close()
+    return [a.reshape(-1) for a in m]
+
+
+def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0):
+    import torch
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = pond.pond_server_create(arena.data_ptr(), arena_bytes, 0, max_active)
+    ids = []
+    try:
+        for k, (wl, steps) in enumerate(jobs):
+            cfg = pond.make_config(wl, precision=pond.POND_MIXED)
+            ids.append(pond.pond_submit(srv, cfg, *wl.fields(), steps, tag=k))
+        out = {}
+        t_end = time.time() + timeout
+        while len(out) < len(ids):
+            assert time.time() < t_end, "serving did not finish"
+            for k, rid in enumerate(ids):
+                if k in out:
+                    continue
+                wl, _ = jobs[k]
+                rc, m, times = pond.pond_poll(srv, rid, wl.nx * wl.ny)
+                if rc != pond.POND_PENDING:
+                    out[k] = (rc, m, times)
+            time.sleep(0.002)
+        return out
+    finally:
+        pond.pond_server_destroy(srv)
+        del arena
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(pond):
+    jobs = _mix()
+    got = _serve(pond, jobs, 1 << 30)
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, times = got[k]
+        assert rc == pond.POND_OK
+        assert times["tag"] == k
+        assert times["t_submit"] <= times["t_admit"] <= times["t_done"]
+        ref = _alone(pond, wl, steps)
+        for a, b in zip(m, ref):
+            assert np.array_equal(a, b), k
+
+
+def test_admission_waits_for_memory(pond):
+    jobs = [(inputs.quadrants_2d(96, steps=1, seed=30 + k), 30) for k in range(5)]
+    one = pond.pond_state_bytes(pond.make_config(jobs[0][0], precision=pond.POND_MIXED))
+    # room for two resident solves (plus the batch table)
+    got = _serve(pond, jobs, 2 * one + (1 << 20))
+    assert all(got[k][0] == pond.POND_OK for k in range(5))
+    t = sorted((got[k][2]["t_admit"], got[k][2]["t_done"]) for k in range(5))
+    # at any admission time at most two solves are resident
+    for ta, _ in t:
+        resident = sum(1 for a, d in t if a <= ta < d)
+        assert resident <= 2
+    assert max(a for a, _ in t) >= min(d for _, d in t)  # someone waited for memory
+    for k, (wl, steps) in enumerate(jobs):
+        for a, b in zip(got[k][1], _alone(pond, wl, steps)):
+            assert np.array_equal(a, b)
+
+
+def test_oversize_request_is_rejected(pond):
+    import torch
+    wl = inputs.quadrants_2d(256, steps=1)
+    cfg = pond.make_config(wl, precision=pond.POND_MIXED)
+    need = pond.pond_state_bytes(cfg)
+    arena = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    srv = pond.pond_server_create(arena.data_ptr(), need // 2, 0, 4)
+    try:
+        with pytest.raises(pond.PondError) as e:
+            pond.pond_submit(srv, cfg, *wl.fields(), 10)
+        assert e.value.code == -5
+    finally:
+        pond.pond_server_destroy(srv)
+
+
+def test_a_failing_solve_does_not_touch_the_others(pond):
+    jobs = _mix()[:3]
+    bad = inputs.quadrants_2d(64, steps=1, seed=99)
+    bad.cfl = 12.0  # far beyond the scheme's stability limit
+    jobs.insert(1, (bad, 200))
+    got = _serve(pond, jobs, 1 << 30)
+    assert got[1][0] == -4  # POND_ERR_UNSTABLE
+    for k in (0, 2, 3):
+        wl, steps = jobs[k]
+        assert got[k][0] == pond.POND_OK
+        for a, b in zip(got[k][1], _alone(pond, wl, steps)):
+            assert np.array_equal(a, b)
