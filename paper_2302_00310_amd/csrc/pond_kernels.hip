@@ -155,55 +155,77 @@ __device__ __forceinline__ void transform(double rt_src, double ux_src, double u
 }
 
 // The same map restricted to the outputs whose transverse index (i_y for an
-// x-face, i_x for a y-face) lies in [K0, K0 + NK); out is indexed
-// j = n + Q1 t (n: normal index, t = transverse index - K0).  The transverse
-// factor is applied first, so only the NK needed rows of it are formed.
-template <int D, int Q1, typename T, int AXIS, int K0, int NK>
-__device__ __forceinline__ void transform_part(double rt_src, double ux_src, double uy_src,
-                                               double irt_dst, double ux_dst, double uy_dst,
-                                               const T* in, T* out) {
-  if constexpr (D == 1) {
-    transform<D, Q1, T>(rt_src, ux_src, uy_src, irt_dst, ux_dst, uy_dst, in, out);
-  } else {
-    const T s = T(rt_src * irt_dst);
-    const T dn = T(((AXIS == 0 ? ux_src : uy_src) - (AXIS == 0 ? ux_dst : uy_dst)) * irt_dst);
-    const T dt = T(((AXIS == 0 ? uy_src : ux_src) - (AXIS == 0 ? uy_dst : ux_dst)) * irt_dst);
-    // stride of the normal / transverse axis in the population index
-    constexpr int SN = AXIS == 0 ? 1 : Q1, ST = AXIS == 0 ? Q1 : 1;
-    T Z[NK][Q1];  // Z[t][mn] = sum_mt A_t[K0 + t][mt] in[mn SN + mt ST]
-    {
-      LagPoint<Q1, T> E[Q1];
+// x-face, i_x for a y-face) lies in [K0, K0 + NK), given the 2D frame shift as
+// s = sqrt(T/T'), dn / dt = normal / transverse (u - u')/sqrt(T'); out is
+// indexed j = n + Q1 t (n: normal index, t = transverse index - K0).  The
+// transverse factor is applied first, only the NK needed rows of it.  The
+// normal factor goes through node-pair sums: for D1Q4,
+// l_{-+B}(x) = p(x) (B -+ x) and l_{-+A}(x) = q(x) (A -+ x), so
+// sum_m l_{-+B}(xi_m) Z_m = B sum p Z -+ sum p xi Z (likewise for A); for
+// D1Q3, l_{-+R3} = (x^2 -+ R3 x)/6 and l_0 = 1 - x^2/3.
+template <int Q1, typename T, int AXIS, int K0, int NK>
+__device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* out) {
+  constexpr int SN = AXIS == 0 ? 1 : Q1, ST = AXIS == 0 ? Q1 : 1;
+  T Z[NK][Q1];  // Z[t][mn] = sum_mt A_t[K0 + t][mt] in[mn SN + mt ST]
+  {
+    LagPoint<Q1, T> E[Q1];
 #pragma unroll
-      for (int m = 0; m < Q1; ++m) E[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dt);
+    for (int m = 0; m < Q1; ++m) E[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dt);
 #pragma unroll
-      for (int t = 0; t < NK; ++t) {
-        T row[Q1];
-#pragma unroll
-        for (int mt = 0; mt < Q1; ++mt) row[mt] = lag_entry<Q1, T>(K0 + t, E[mt]);
-#pragma unroll
-        for (int mn = 0; mn < Q1; ++mn) {
-          T acc = row[0] * in[mn * SN];
-#pragma unroll
-          for (int mt = 1; mt < Q1; ++mt) acc += row[mt] * in[mn * SN + mt * ST];
-          Z[t][mn] = acc;
-        }
-      }
-    }
-    LagPoint<Q1, T> X[Q1];
-#pragma unroll
-    for (int m = 0; m < Q1; ++m) X[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dn);
-#pragma unroll
-    for (int n = 0; n < Q1; ++n) {
+    for (int t = 0; t < NK; ++t) {
       T row[Q1];
 #pragma unroll
-      for (int mn = 0; mn < Q1; ++mn) row[mn] = lag_entry<Q1, T>(n, X[mn]);
+      for (int mt = 0; mt < Q1; ++mt) row[mt] = lag_entry<Q1, T>(K0 + t, E[mt]);
 #pragma unroll
-      for (int t = 0; t < NK; ++t) {
-        T acc = row[0] * Z[t][0];
+      for (int mn = 0; mn < Q1; ++mn) {
+        T acc = row[0] * in[mn * SN];
 #pragma unroll
-        for (int mn = 1; mn < Q1; ++mn) acc += row[mn] * Z[t][mn];
-        out[n + Q1 * t] = acc;
+        for (int mt = 1; mt < Q1; ++mt) acc += row[mt] * in[mn * SN + mt * ST];
+        Z[t][mn] = acc;
       }
+    }
+  }
+  T xi[Q1];
+#pragma unroll
+  for (int m = 0; m < Q1; ++m) xi[m] = s * node<Q1, T>(m) + dn;
+  if constexpr (Q1 == 4) {
+    T p[4], q[4], px[4], qx[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const T x2 = xi[m] * xi[m];
+      p[m] = (x2 - T(kA2)) * T(kKB);
+      q[m] = (x2 - T(kB2)) * T(kKA);
+      px[m] = p[m] * xi[m];
+      qx[m] = q[m] * xi[m];
+    }
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      T P0 = p[0] * Z[t][0], P1 = px[0] * Z[t][0], Q0 = q[0] * Z[t][0], Qs = qx[0] * Z[t][0];
+#pragma unroll
+      for (int m = 1; m < 4; ++m) {
+        P0 += p[m] * Z[t][m];
+        P1 += px[m] * Z[t][m];
+        Q0 += q[m] * Z[t][m];
+        Qs += qx[m] * Z[t][m];
+      }
+      out[0 + 4 * t] = T(kB) * P0 - P1;
+      out[1 + 4 * t] = T(kA) * Q0 - Qs;
+      out[2 + 4 * t] = T(kA) * Q0 + Qs;
+      out[3 + 4 * t] = T(kB) * P0 + P1;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+      T S0 = Z[t][0], S1 = xi[0] * Z[t][0], S2 = xi[0] * xi[0] * Z[t][0];
+#pragma unroll
+      for (int m = 1; m < 3; ++m) {
+        S0 += Z[t][m];
+        S1 += xi[m] * Z[t][m];
+        S2 += xi[m] * xi[m] * Z[t][m];
+      }
+      out[0 + 3 * t] = (S2 - T(kR3) * S1) * T(1.0 / 6.0);
+      out[1 + 3 * t] = S0 - S2 * T(1.0 / 3.0);
+      out[2 + 3 * t] = (S2 + T(kR3) * S1) * T(1.0 / 6.0);
     }
   }
 }
@@ -470,6 +492,7 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
   using G = Geo<D>;
   constexpr int Q = D == 2 ? Q1 * Q1 : Q1;  // populations of the lattice
   constexpr int NQ = D == 2 ? Q1 * NK : Q1; // populations of this part
+  // stencil cell `slot` in the face frame
   auto tfs = [&](int slot, T* out) {
     // compiler-only memory fence: the LDS loads of one stencil cell are not
     // hoisted above the work of the previous one
@@ -478,8 +501,14 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
     T in[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
-    transform_part<D, Q1, T, AXIS, K0, NK>(sm.RT[h], sm.U[h], D == 2 ? sm.V[h] : 0.0, irtF, uF,
-                                           vF, in, out);
+    if constexpr (D == 2) {
+      const T s = T(sm.RT[h] * irtF);
+      const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
+      const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
+      transform_part<Q1, T, AXIS, K0, NK>(s, dn, dt, in, out);
+    } else {
+      transform<1, Q1, T>(sm.RT[h], sm.U[h], 0.0, irtF, uF, 0.0, in, out);
+    }
     // keep the scheduler from overlapping the stencil cells' transforms
     // (each one holds its own LDS loads and coefficients in registers)
     __builtin_amdgcn_sched_barrier(0);
