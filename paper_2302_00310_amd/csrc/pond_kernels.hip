@@ -29,7 +29,7 @@ namespace pond {
 namespace {
 
 constexpr int BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1;
-constexpr int LIM_MINMOD = 1;
+constexpr int LIM_VANLEER = 0, LIM_MINMOD = 1;
 constexpr double kTieBand = 1e-11;  // |v_n| <= kTieBand sqrt(T_F): upwind tie
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
@@ -245,9 +245,9 @@ __device__ __forceinline__ void eq_factor(T s, T d, T (&out)[Q1]) {
 }
 
 // Slope limiters (Sec. IV A 2): van Leer (a|b| + |a|b) / (|a| + |b|), minmod.
-template <typename T>
-__device__ __forceinline__ T limit(int kind, T a, T b) {
-  if (kind == LIM_MINMOD) {
+template <int LIM, typename T>
+__device__ __forceinline__ T limit(T a, T b) {
+  if constexpr (LIM == LIM_MINMOD) {
     if (a * b <= T(0)) return T(0);
     return a > T(0) ? fmin(a, b) : fmax(a, b);
   }
@@ -485,7 +485,7 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
 // operands of the two limiters are selected per population, so each
 // population costs one normal and one transverse limiter; ties take a second
 // pass.
-template <int D, int Q1, typename T, int AXIS, int K0, int NK>
+template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM>
 __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>& sm,
                                             const int (&st)[Geo<D>::NS], int plane0, double rtF,
                                             double irtF, double uF, double vF, T* bar) {
@@ -521,8 +521,9 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {
     const double v = rtF * node<Q1, double>(nidx(j)) + (AXIS == 0 ? uF : vF);
-    if (!(v < -band)) left |= 1u << j;
-    if (!(v < -band) && !(v > band)) tie |= 1u << j;
+    const unsigned l = !(v < -band), t = l & unsigned(!(v > band));
+    left |= l << j;
+    tie |= t << j;
   }
   // departure-point offsets in cell units: normal -v_n dt/(2 dx) (+-1/2 from
   // the upwind centre), transverse -v_t dt/(2 dx)
@@ -547,7 +548,7 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
       const T mid = PR[j] - PL[j];
       const T sa = l ? X[j] : mid, sb = l ? mid : t[j] - PR[j];
       const T dn = (l ? T(0.5) : T(-0.5)) - hl * vnorm(j);
-      rec[j] = (l ? PL[j] : PR[j]) + dn * limit(a.limiter, sa, sb);
+      rec[j] = (l ? PL[j] : PR[j]) + dn * limit<LIM>(sa, sb);
     }
   }
   if constexpr (D == 2) {
@@ -569,7 +570,7 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
       for (int j = 0; j < NQ; ++j) ta[j] = isl(j) ? ta[j] : PR[j] - t[j];
     }
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) rec[j] += dtrans(j) * limit(a.limiter, ta[j], tb[j]);
+    for (int j = 0; j < NQ; ++j) rec[j] += dtrans(j) * limit<LIM>(ta[j], tb[j]);
   }
   if (tie) {
     // ties: the right-upwind reconstruction, then the mean of both
@@ -577,13 +578,13 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
     tfs(3, t);
 #pragma unroll
     for (int j = 0; j < NQ; ++j)
-      rr[j] = PR[j] + (T(-0.5) - hl * vnorm(j)) * limit(a.limiter, PR[j] - PL[j], t[j] - PR[j]);
+      rr[j] = PR[j] + (T(-0.5) - hl * vnorm(j)) * limit<LIM>(PR[j] - PL[j], t[j] - PR[j]);
     if constexpr (D == 2) {
       T tp[NQ];
       tfs(6, tp);
       tfs(7, t);
 #pragma unroll
-      for (int j = 0; j < NQ; ++j) rr[j] += dtrans(j) * limit(a.limiter, PR[j] - t[j], tp[j] - PR[j]);
+      for (int j = 0; j < NQ; ++j) rr[j] += dtrans(j) * limit<LIM>(PR[j] - t[j], tp[j] - PR[j]);
     }
 #pragma unroll
     for (int j = 0; j < NQ; ++j)
@@ -593,10 +594,105 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
   for (int j = 0; j < NQ; ++j) bar[j] = rec[j];
 }
 
-template <int D, typename T, int AXIS>
+// Whether a population's normal velocity at the face lies in the tie band.
+template <int Q1, int AXIS>
+__device__ __forceinline__ bool tied(double rtF, double uF, double vF) {
+  const double band = kTieBand * rtF;
+  bool t = false;
+#pragma unroll
+  for (int n = 0; n < Q1; ++n) t |= fabs(rtF * node<Q1, double>(n) + (AXIS == 0 ? uF : vF)) <= band;
+  return t;
+}
+
+// The same reconstruction for all Q1 x Q1 populations of one 2D lattice at
+// once (out indexed j = n + Q1 t), walking the stencil one cell at a time:
+// each cell is transformed into the face frame whole and folded into the
+// running limiter operands, so the frame-dependent coefficients of a cell are
+// formed once per face rather than once per transverse row.  Faces where a
+// population's normal velocity falls in the tie band take the row-wise path.
+template <int Q1, typename T, int AXIS, int LIM>
+__device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& sm,
+                                                 const int (&st)[Geo<2>::NS], int plane0,
+                                                 int fidx, double rtF, double irtF, double uF,
+                                                 double vF, T* out) {
+  using G = Geo<2>;
+  constexpr int Q = Q1 * Q1;
+  auto tfs = [&](int slot, T* o) {
+    // compiler-only memory fence: the LDS loads of one stencil cell are not
+    // hoisted above the work of the previous one
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+    const int h = st[slot];
+    T in[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
+    const T s = T(sm.RT[h] * irtF);
+    const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
+    const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
+    transform_part<Q1, T, AXIS, 0, Q1>(s, dn, dt, in, o);
+    // the empty asm pins the finished outputs: without it the compiler sinks
+    // parts of the transform into the consumers and keeps its operands live
+    // across the next cells (spills)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(o[i]));
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // the upwind side depends on the normal node only (bit n), decided in FP64;
+  // the caller has ruled out ties
+  unsigned left = 0;
+#pragma unroll
+  for (int n = 0; n < Q1; ++n)
+    left |= unsigned(rtF * node<Q1, double>(n) + (AXIS == 0 ? uF : vF) > 0.0) << n;
+  const T rtT = T(rtF), unT = T(AXIS == 0 ? uF : vF), utT = T(AXIS == 0 ? vF : uF);
+  const T hl = T(0.5 * a.lam);
+  auto isl = [&](int j) { return (left >> (j % Q1)) & 1u; };
+  auto vnorm = [&](int j) { return rtT * node<Q1, T>(j % Q1) + unT; };
+  auto dtrans = [&](int j) { return -hl * (rtT * node<Q1, T>(j / Q1) + utT); };
+  // the partial reconstruction waits in this face's slot of the face buffer
+  // (indexed by j) while the transverse neighbours are transformed
+  auto park = [&](int j) -> T& { return sm.F[(plane0 + j) * G::NF + fidx]; };
+  T PL[Q], PR[Q], S[Q], TB[Q];
+  tfs(0, PL);
+  tfs(1, PR);
+  {
+    T t[Q];
+    tfs(2, t);  // first normal-limiter operand
+#pragma unroll
+    for (int j = 0; j < Q; ++j) S[j] = isl(j) ? PL[j] - t[j] : PR[j] - PL[j];
+    tfs(3, t);  // second operand, then the normal slope term at the upwind cell
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const bool l = isl(j);
+      const T sb = l ? PR[j] - PL[j] : t[j] - PR[j];
+      const T dn = (l ? T(0.5) : T(-0.5)) - hl * vnorm(j);
+      park(j) = (l ? PL[j] : PR[j]) + dn * limit<LIM>(S[j], sb);
+    }
+    // transverse slope term: left-upwind populations from L's neighbours
+    // (4, 5), added to the parked value, then right-upwind ones from R's (6, 7)
+    tfs(4, t);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) TB[j] = t[j] - PL[j];
+    tfs(5, t);
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (isl(j)) park(j) += dtrans(j) * limit<LIM>(PL[j] - t[j], TB[j]);
+    tfs(6, t);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) TB[j] = t[j] - PR[j];
+    tfs(7, t);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) S[j] = isl(j) ? T(0) : dtrans(j) * limit<LIM>(PR[j] - t[j], TB[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) out[j] = park(j) + S[j];
+}
+
+template <int D, typename T, int AXIS, int LIM>
 __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG;
+  // FP32 reconstructs each lattice whole, FP64 one transverse row at a time
+  constexpr bool kWhole = sizeof(T) == 4;
   const int hL = st[0], hR = st[1];
   // eq. AvgFrame
   double uF = 0.5 * (sm.U[hL] + sm.U[hR]);
@@ -626,34 +722,54 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
       }
     };
     if constexpr (D == 2) {
-      // one row of the transverse index at a time keeps the reconstruction
-      // within the register budget of two workgroups per CU
-      constexpr int NK = 1;
-      static_for<0, 4 / NK>([&](auto part) {
-        constexpr int K0 = decltype(part)::value * NK;
-        T bar[4 * NK];
-        reconstruct<D, 4, T, AXIS, K0, NK>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
-        take_f(bar, K0, NK);
-      });
+      if (kWhole && !tied<4, AXIS>(rtF, uF, vF)) {
+        T bar[QF];
+        reconstruct_full<4, T, AXIS, LIM>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
+        take_f(bar, 0, 4);
+      } else {
+        // one row of the transverse index at a time (FP64 register budget,
+        // or a tie to resolve)
+        static_for<0, 4>([&](auto part) {
+          constexpr int K0 = decltype(part)::value;
+          T bar[4];
+          reconstruct<D, 4, T, AXIS, K0, 1, LIM>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+          take_f(bar, K0, 1);
+        });
+      }
     } else {
       T bar[4];
-      reconstruct<D, 4, T, AXIS, 0, 1>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+      reconstruct<D, 4, T, AXIS, 0, 1, LIM>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
       take_f(bar, 0, 1);
     }
-    {
-      constexpr int NKG = 1;
-      static_for<0, (D == 2 ? 3 / NKG : 1)>([&](auto part) {
-        constexpr int K0 = decltype(part)::value * NKG;
-        T gbar[3 * NKG];
-        reconstruct<D, 3, T, AXIS, K0, NKG>(a, sm, st, QF, rtF, irtF, uF, vF, gbar);
+    auto g_rows = [&]() {
+      static_for<0, (D == 2 ? 3 : 1)>([&](auto part) {
+        constexpr int K0 = decltype(part)::value;
+        T gbar[3];
+        reconstruct<D, 3, T, AXIS, K0, 1, LIM>(a, sm, st, QF, rtF, irtF, uF, vF, gbar);
 #pragma unroll
-        for (int j = 0; j < 3 * NKG; ++j) {
-          const int n = j % 3, t = K0 + j / 3;
-          const int i = D == 1 ? n : (AXIS == 0 ? n + 3 * t : t + 3 * n);
+        for (int j = 0; j < 3; ++j) {
+          const int i = D == 1 ? j : (AXIS == 0 ? j + 3 * K0 : K0 + 3 * j);
           e += double(gbar[j]);
           sm.F[(QF + i) * G::NF + fidx] = gbar[j];
         }
       });
+    };
+    if constexpr (D == 2) {
+      if (kWhole && !tied<3, AXIS>(rtF, uF, vF)) {
+        T gbar[QG];
+        reconstruct_full<3, T, AXIS, LIM>(a, sm, st, QF, fidx, rtF, irtF, uF, vF, gbar);
+#pragma unroll
+        for (int j = 0; j < QG; ++j) {
+          const int n = j % 3, t = j / 3;
+          const int i = AXIS == 0 ? n + 3 * t : t + 3 * n;
+          e += double(gbar[j]);
+          sm.F[(QF + i) * G::NF + fidx] = gbar[j];
+        }
+      } else {
+        g_rows();
+      }
+    } else {
+      g_rows();
     }
     rho_b = m0;
     ub = mx / m0;
@@ -779,7 +895,7 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
 // --------------------------------------------------------------------------
 // The fused step kernel.
 // --------------------------------------------------------------------------
-template <int D, typename T>
+template <int D, typename T, int LIM>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
@@ -810,23 +926,20 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     sm.RT[h] = fr.rt;
   }
   __syncthreads();
-  // the thread's own cell (interior slot tid)
+  // the thread's own cell (interior slot tid); its frame is read from LDS
+  // where it is needed, so that nothing of it is held through the face phases
   const int cx = tid % G::TX, cy = tid / G::TX;
   const bool own_in = tid < G::NI && x0 + cx < a.nx && (D == 1 || y0 + cy < a.ny);
-  Frame ownF{};
-  if (tid < G::NI) {
+  auto own_frame = [&]() {
+    Frame f{};
     const int h = cx + 2 + G::HX * (cy + G::OY);
-    ownF.ux = sm.U[h];
-    ownF.uy = sm.V[h];
-    ownF.T = sm.RT[h] * sm.RT[h];
-    ownF.rt = sm.RT[h];
-    ownF.irt = 1.0 / ownF.rt;
-  }
-
-  T acc[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) acc[i] = T(0);
-  long long dU[4] = {0, 0, 0, 0};
+    f.ux = sm.U[h];
+    f.uy = sm.V[h];
+    f.T = sm.RT[h] * sm.RT[h];
+    f.rt = sm.RT[h];
+    f.irt = 1.0 / f.rt;
+    return f;
+  };
 
   // ---- 1. x-faces
   if (tid < G::NFX) {
@@ -844,13 +957,17 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       st[6] = hL + 1 + G::HX;
       st[7] = hL + 1 - G::HX;
     }
-    face_eval<D, T, 0>(a, sm, st, tid);
+    face_eval<D, T, 0, LIM>(a, sm, st, tid);
   }
   __syncthreads();
   // ---- 2. west/east faces into the cell frame
+  T acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = T(0);
+  long long dU[4] = {0, 0, 0, 0};
   if (tid < G::NI) {
     const int fw = cx + (G::TX + 1) * cy;
-    gather_faces<D, T, 0>(sm, fw, fw + 1, ownF, acc);
+    gather_faces<D, T, 0>(sm, fw, fw + 1, own_frame(), acc);
     long long pw[4], pe[4];
     __builtin_amdgcn_sched_barrier(0);
     face_flux<D, T, 0>(a, sm, fw, pw);
@@ -882,7 +999,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       st[5] = hS - 1;
       st[6] = hS + G::HX + 1;
       st[7] = hS + G::HX - 1;
-      face_eval<D, T, 1>(a, sm, st, tid);
+      face_eval<D, T, 1, LIM>(a, sm, st, tid);
     }
     __syncthreads();
     // ---- 4. south/north faces
@@ -892,7 +1009,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     }
     if (tid < G::NI) {
       const int fs = cx + G::TX * cy;
-      gather_faces<D, T, 1>(sm, fs, fs + G::TX, ownF, acc);
+      gather_faces<D, T, 1>(sm, fs, fs + G::TX, own_frame(), acc);
       long long ps[4], pn[4];
       __builtin_amdgcn_sched_barrier(0);
       face_flux<D, T, 1>(a, sm, fs, ps);
@@ -951,7 +1068,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
 template <int D, typename T>
 __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) step_kernel(StepArgs a) {
   __shared__ Smem<D, T> sm;
-  step_tile<D, T>(a, blockIdx.x, sm);
+  // the limiter is uniform over a launch: one straight-line body per kind
+  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD>(a, blockIdx.x, sm);
+  else step_tile<D, T, LIM_VANLEER>(a, blockIdx.x, sm);
 }
 
 // A ragged batch of independent solves in one launch: block b advances tile
@@ -967,8 +1086,12 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
     const int mid = (lo + hi + 1) >> 1;
     if (tab[mid].tile_begin <= b) lo = mid; else hi = mid - 1;
   }
-  const BatchEntry& e = tab[lo];
-  step_tile<D, T>(e.args[parity], b - e.tile_begin, sm);
+  // copied before the first store, so the uniform loads stay scalar
+  const StepArgs a = tab[lo].args[parity];
+  const int tile = b - tab[lo].tile_begin;
+  // the limiter is uniform over a solve: one straight-line body per kind
+  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD>(a, tile, sm);
+  else step_tile<D, T, LIM_VANLEER>(a, tile, sm);
 }
 
 // --------------------------------------------------------------------------
