@@ -92,11 +92,66 @@ __device__ __forceinline__ T lag_entry(int k, const LagPoint<Q1, T>& L) {
   }
 }
 
+// sum_m l_k(x_m) v_m for every node k, through node-pair sums: for D1Q4,
+// l_{-+B}(x) = p(x) (B -+ x) and l_{-+A}(x) = q(x) (A -+ x), so the pair's two
+// outputs are B sum p v -+ sum p x v (likewise for A); for D1Q3,
+// l_{-+R3} = (x^2 -+ R3 x)/6 and l_0 = 1 - x^2/3.
+template <int Q1, typename T>
+struct PairBasis {
+  T c0[Q1], c1[Q1], c2[Q1], c3[Q1];  // D1Q4: p, p x, q, q x; D1Q3: x, x^2
+  __device__ __forceinline__ explicit PairBasis(const T* x) {
+#pragma unroll
+    for (int m = 0; m < Q1; ++m) {
+      const T x2 = x[m] * x[m];
+      if constexpr (Q1 == 4) {
+        c0[m] = (x2 - T(kA2)) * T(kKB);
+        c2[m] = (x2 - T(kB2)) * T(kKA);
+        c1[m] = c0[m] * x[m];
+        c3[m] = c2[m] * x[m];
+      } else {
+        c0[m] = x[m];
+        c1[m] = x2;
+      }
+    }
+  }
+  // v[m * SV] -> o[k * SO]
+  template <int SV, int SO>
+  __device__ __forceinline__ void apply(const T* v, T* o) const {
+    if constexpr (Q1 == 4) {
+      T P0 = c0[0] * v[0], P1 = c1[0] * v[0], Q0 = c2[0] * v[0], Qs = c3[0] * v[0];
+#pragma unroll
+      for (int m = 1; m < 4; ++m) {
+        P0 += c0[m] * v[m * SV];
+        P1 += c1[m] * v[m * SV];
+        Q0 += c2[m] * v[m * SV];
+        Qs += c3[m] * v[m * SV];
+      }
+      o[0] = T(kB) * P0 - P1;
+      o[SO] = T(kA) * Q0 - Qs;
+      o[2 * SO] = T(kA) * Q0 + Qs;
+      o[3 * SO] = T(kB) * P0 + P1;
+    } else {
+      T S0 = v[0], S1 = c0[0] * v[0], S2 = c1[0] * v[0];
+#pragma unroll
+      for (int m = 1; m < 3; ++m) {
+        S0 += v[m * SV];
+        S1 += c0[m] * v[m * SV];
+        S2 += c1[m] * v[m * SV];
+      }
+      o[0] = (S2 - T(kR3) * S1) * T(1.0 / 6.0);
+      o[SO] = S0 - S2 * T(1.0 / 3.0);
+      o[2 * SO] = (S2 + T(kR3) * S1) * T(1.0 / 6.0);
+    }
+  }
+};
+
 // Moment-matching map (App. B) of one lattice's populations from a frame
 // with (sqrt T, u) to the frame with (1/sqrt T', u'): on the tensor lattice
 // G = A_x (x) A_y with A[k][m] = l_k(xi_m), xi_m = s c_m + d, s = sqrt(T/T'),
-// d = (u - u')/sqrt(T').  Applied factor by factor, coefficient rows formed
-// on the fly so that only the point factors stay in registers.
+// d = (u - u')/sqrt(T'), applied factor by factor (transform_part below).
+template <int Q1, typename T, int AXIS, int K0, int NK>
+__device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* out);
+
 template <int D, int Q1, typename T>
 __device__ __forceinline__ void transform(double rt_src, double ux_src, double uy_src,
                                           double irt_dst, double ux_dst, double uy_dst,
@@ -104,70 +159,34 @@ __device__ __forceinline__ void transform(double rt_src, double ux_src, double u
   const T s = T(rt_src * irt_dst);
   const T dx = T((ux_src - ux_dst) * irt_dst);
   if constexpr (D == 1) {
-    LagPoint<Q1, T> X[Q1];
+    T x[Q1];
 #pragma unroll
-    for (int m = 0; m < Q1; ++m) X[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dx);
-#pragma unroll
-    for (int k = 0; k < Q1; ++k) {
-      T acc = lag_entry<Q1, T>(k, X[0]) * in[0];
-#pragma unroll
-      for (int m = 1; m < Q1; ++m) acc += lag_entry<Q1, T>(k, X[m]) * in[m];
-      out[k] = acc;
-    }
+    for (int m = 0; m < Q1; ++m) x[m] = s * node<Q1, T>(m) + dx;
+    PairBasis<Q1, T>(x).template apply<1, 1>(in, out);
   } else {
-    T Y[Q1][Q1];  // Y[mx][ky] = sum_my A_y[ky][my] in[mx + Q1 my]
-    {
-      LagPoint<Q1, T> E[Q1];
-      const T dy = T((uy_src - uy_dst) * irt_dst);
-#pragma unroll
-      for (int m = 0; m < Q1; ++m) E[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dy);
-#pragma unroll
-      for (int ky = 0; ky < Q1; ++ky) {
-        T row[Q1];
-#pragma unroll
-        for (int my = 0; my < Q1; ++my) row[my] = lag_entry<Q1, T>(ky, E[my]);
-#pragma unroll
-        for (int mx = 0; mx < Q1; ++mx) {
-          T acc = row[0] * in[mx];
-#pragma unroll
-          for (int my = 1; my < Q1; ++my) acc += row[my] * in[mx + Q1 * my];
-          Y[mx][ky] = acc;
-        }
-      }
-    }
-    LagPoint<Q1, T> X[Q1];
-#pragma unroll
-    for (int m = 0; m < Q1; ++m) X[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dx);
-#pragma unroll
-    for (int kx = 0; kx < Q1; ++kx) {
-      T row[Q1];
-#pragma unroll
-      for (int mx = 0; mx < Q1; ++mx) row[mx] = lag_entry<Q1, T>(kx, X[mx]);
-#pragma unroll
-      for (int ky = 0; ky < Q1; ++ky) {
-        T acc = row[0] * Y[0][ky];
-#pragma unroll
-        for (int mx = 1; mx < Q1; ++mx) acc += row[mx] * Y[mx][ky];
-        out[kx + Q1 * ky] = acc;
-      }
-    }
+    transform_part<Q1, T, 0, 0, Q1>(s, dx, T((uy_src - uy_dst) * irt_dst), in, out);
   }
 }
+
 
 // The same map restricted to the outputs whose transverse index (i_y for an
 // x-face, i_x for a y-face) lies in [K0, K0 + NK), given the 2D frame shift as
 // s = sqrt(T/T'), dn / dt = normal / transverse (u - u')/sqrt(T'); out is
 // indexed j = n + Q1 t (n: normal index, t = transverse index - K0).  The
-// transverse factor is applied first, only the NK needed rows of it.  The
-// normal factor goes through node-pair sums: for D1Q4,
-// l_{-+B}(x) = p(x) (B -+ x) and l_{-+A}(x) = q(x) (A -+ x), so
-// sum_m l_{-+B}(xi_m) Z_m = B sum p Z -+ sum p xi Z (likewise for A); for
-// D1Q3, l_{-+R3} = (x^2 -+ R3 x)/6 and l_0 = 1 - x^2/3.
+// transverse factor is applied first: whole through node-pair sums, or only
+// the NK needed rows of it.  The normal factor goes through node-pair sums.
 template <int Q1, typename T, int AXIS, int K0, int NK>
 __device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* out) {
   constexpr int SN = AXIS == 0 ? 1 : Q1, ST = AXIS == 0 ? Q1 : 1;
   T Z[NK][Q1];  // Z[t][mn] = sum_mt A_t[K0 + t][mt] in[mn SN + mt ST]
-  {
+  if constexpr (NK == Q1) {
+    T xt[Q1];
+#pragma unroll
+    for (int m = 0; m < Q1; ++m) xt[m] = s * node<Q1, T>(m) + dt;
+    const PairBasis<Q1, T> bt(xt);
+#pragma unroll
+    for (int mn = 0; mn < Q1; ++mn) bt.template apply<ST, Q1>(in + mn * SN, &Z[0][mn]);
+  } else {
     LagPoint<Q1, T> E[Q1];
 #pragma unroll
     for (int m = 0; m < Q1; ++m) E[m] = lag_point<Q1, T>(s * node<Q1, T>(m) + dt);
@@ -188,46 +207,9 @@ __device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* 
   T xi[Q1];
 #pragma unroll
   for (int m = 0; m < Q1; ++m) xi[m] = s * node<Q1, T>(m) + dn;
-  if constexpr (Q1 == 4) {
-    T p[4], q[4], px[4], qx[4];
+  const PairBasis<Q1, T> bn(xi);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const T x2 = xi[m] * xi[m];
-      p[m] = (x2 - T(kA2)) * T(kKB);
-      q[m] = (x2 - T(kB2)) * T(kKA);
-      px[m] = p[m] * xi[m];
-      qx[m] = q[m] * xi[m];
-    }
-#pragma unroll
-    for (int t = 0; t < NK; ++t) {
-      T P0 = p[0] * Z[t][0], P1 = px[0] * Z[t][0], Q0 = q[0] * Z[t][0], Qs = qx[0] * Z[t][0];
-#pragma unroll
-      for (int m = 1; m < 4; ++m) {
-        P0 += p[m] * Z[t][m];
-        P1 += px[m] * Z[t][m];
-        Q0 += q[m] * Z[t][m];
-        Qs += qx[m] * Z[t][m];
-      }
-      out[0 + 4 * t] = T(kB) * P0 - P1;
-      out[1 + 4 * t] = T(kA) * Q0 - Qs;
-      out[2 + 4 * t] = T(kA) * Q0 + Qs;
-      out[3 + 4 * t] = T(kB) * P0 + P1;
-    }
-  } else {
-#pragma unroll
-    for (int t = 0; t < NK; ++t) {
-      T S0 = Z[t][0], S1 = xi[0] * Z[t][0], S2 = xi[0] * xi[0] * Z[t][0];
-#pragma unroll
-      for (int m = 1; m < 3; ++m) {
-        S0 += Z[t][m];
-        S1 += xi[m] * Z[t][m];
-        S2 += xi[m] * xi[m] * Z[t][m];
-      }
-      out[0 + 3 * t] = (S2 - T(kR3) * S1) * T(1.0 / 6.0);
-      out[1 + 3 * t] = S0 - S2 * T(1.0 / 3.0);
-      out[2 + 3 * t] = (S2 + T(kR3) * S1) * T(1.0 / 6.0);
-    }
-  }
+  for (int t = 0; t < NK; ++t) bn.template apply<1, 1>(Z[t], out + Q1 * t);
 }
 
 // Quadrature of the Lagrange basis against the weights:
@@ -691,8 +673,8 @@ template <int D, typename T, int AXIS, int LIM>
 __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG;
-  // FP32 reconstructs each lattice whole, FP64 one transverse row at a time
-  constexpr bool kWhole = sizeof(T) == 4;
+  // each lattice is reconstructed whole unless a tie needs the row-wise path
+  constexpr bool kWhole = true;
   const int hL = st[0], hR = st[1];
   // eq. AvgFrame
   double uF = 0.5 * (sm.U[hL] + sm.U[hR]);
@@ -727,8 +709,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
         reconstruct_full<4, T, AXIS, LIM>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
         take_f(bar, 0, 4);
       } else {
-        // one row of the transverse index at a time (FP64 register budget,
-        // or a tie to resolve)
+        // one row of the transverse index at a time, resolving ties
         static_for<0, 4>([&](auto part) {
           constexpr int K0 = decltype(part)::value;
           T bar[4];
@@ -1073,6 +1054,17 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) 
   else step_tile<D, T, LIM_VANLEER>(a, blockIdx.x, sm);
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (block b to XCD b mod 8),
+// and each XCD has its own L2.  Renumbering so that XCD x works through one
+// contiguous run of tiles makes neighbouring tiles, which share halo cache
+// lines, meet in the same L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, k = b / kXcd;
+  const int q = nb / kXcd, r = nb % kXcd;
+  return x * q + min(x, r) + k;
+}
+
 // A ragged batch of independent solves in one launch: block b advances tile
 // b - tile_begin of the entry whose tile range holds b.  Each entry carries
 // the arguments of both step parities; step `parity` uses args[parity].
@@ -1081,7 +1073,7 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
     step_batch_kernel(const BatchEntry* tab, int n, int parity) {
   __shared__ Smem<D, T> sm;
   int lo = 0, hi = n - 1;
-  const int b = blockIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
   while (lo < hi) {  // last entry with tile_begin <= b
     const int mid = (lo + hi + 1) >> 1;
     if (tab[mid].tile_begin <= b) lo = mid; else hi = mid - 1;
