@@ -104,8 +104,8 @@ struct PairBasis {
     for (int m = 0; m < Q1; ++m) {
       const T x2 = x[m] * x[m];
       if constexpr (Q1 == 4) {
-        c0[m] = (x2 - T(kA2)) * T(kKB);
-        c2[m] = (x2 - T(kB2)) * T(kKA);
+        c0[m] = x2 * T(kKB) + T(-kA2 * kKB);
+        c2[m] = x2 * T(kKA) + T(-kB2 * kKA);
         c1[m] = c0[m] * x[m];
         c3[m] = c2[m] * x[m];
       } else {
@@ -656,8 +656,10 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
     for (int j = 0; j < Q; ++j) TB[j] = t[j] - PL[j];
     tfs(5, t);
 #pragma unroll
-    for (int j = 0; j < Q; ++j)
-      if (isl(j)) park(j) += dtrans(j) * limit<LIM>(PL[j] - t[j], TB[j]);
+    for (int j = 0; j < Q; ++j) {
+      const T d = dtrans(j) * limit<LIM>(PL[j] - t[j], TB[j]);
+      park(j) += isl(j) ? d : T(0);
+    }
     tfs(6, t);
 #pragma unroll
     for (int j = 0; j < Q; ++j) TB[j] = t[j] - PR[j];
@@ -707,7 +709,33 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
       if (kWhole && !tied<4, AXIS>(rtF, uF, vF)) {
         T bar[QF];
         reconstruct_full<4, T, AXIS, LIM>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
-        take_f(bar, 0, 4);
+        // moments through row sums R_n (over t) and column sums C_t (over n)
+        const double un = AXIS == 0 ? uF : vF, ut = AXIS == 0 ? vF : uF;
+        double C[4] = {0.0, 0.0, 0.0, 0.0}, mn = 0.0, mt = 0.0, e2 = 0.0;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          double R = 0.0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double fb = double(bar[n + 4 * t]);
+            R += fb;
+            C[t] += fb;
+            sm.F[(AXIS == 0 ? n + 4 * t : t + 4 * n) * G::NF + fidx] = bar[n + 4 * t];
+          }
+          const double vn = rtF * node<4, double>(n) + un;
+          m0 += R;
+          mn += vn * R;
+          e2 += vn * vn * R;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double vt = rtF * node<4, double>(t) + ut;
+          mt += vt * C[t];
+          e2 += vt * vt * C[t];
+        }
+        mx += AXIS == 0 ? mn : mt;
+        my += AXIS == 0 ? mt : mn;
+        e += 0.5 * e2;
       } else {
         // one row of the transverse index at a time, resolving ties
         static_for<0, 4>([&](auto part) {
@@ -807,22 +835,56 @@ __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& s
   constexpr int QF = G::QF, QG = G::QG;
   const double rtF = sm.FRT[fi], uF = sm.FU[fi], vF = sm.FV[fi];
   double Fr = 0.0, Fx = 0.0, Fy = 0.0, FE = 0.0;
+  if constexpr (D == 2) {
+    // sums over the transverse index first: with n the normal and t the
+    // transverse node, v_n and v_t are per-node and the moments factor as
+    // sums over n of v_n {1, v_n, ., v_n^2/2} times row sums over t
+    const double un = AXIS == 0 ? uF : vF, ut = AXIS == 0 ? vF : uF;
+    double vt[4];
 #pragma unroll
-  for (int i = 0; i < QF; ++i) {
-    const double vx = rtF * node<4, double>(i & 3) + uF;
-    const double vy = D == 2 ? rtF * node<4, double>(i >> 2) + vF : 0.0;
-    const double vn = AXIS == 0 ? vx : vy;
-    const double p = double(sm.F[i * G::NF + fi]) * vn;
-    Fr += p;
-    Fx += vx * p;
-    Fy += vy * p;
-    FE += 0.5 * (vx * vx + vy * vy) * p;
-  }
+    for (int k = 0; k < 4; ++k) vt[k] = rtF * node<4, double>(k) + ut;
+    double Fn = 0.0, Ft = 0.0;
 #pragma unroll
-  for (int i = 0; i < QG; ++i) {
-    const int in_ = AXIS == 0 ? (i % 3) : (i / 3);
-    const double vn = rtF * node<3, double>(in_) + (AXIS == 0 ? uF : vF);
-    FE += vn * double(sm.F[(QF + i) * G::NF + fi]);
+    for (int n = 0; n < 4; ++n) {
+      const double vn = rtF * node<4, double>(n) + un;
+      double R = 0.0, Y = 0.0, Y2 = 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = AXIS == 0 ? n + 4 * t : t + 4 * n;
+        const double f = double(sm.F[i * G::NF + fi]);
+        R += f;
+        Y += vt[t] * f;
+        Y2 += vt[t] * vt[t] * f;
+      }
+      double Rg = 0.0;
+      if (n < 3) {
+        const double vg = rtF * node<3, double>(n) + un;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int i = AXIS == 0 ? n + 3 * t : t + 3 * n;
+          Rg += double(sm.F[(QF + i) * G::NF + fi]);
+        }
+        FE += vg * Rg;
+      }
+      Fr += vn * R;
+      Fn += vn * vn * R;
+      Ft += vn * Y;
+      FE += 0.5 * vn * (vn * vn * R + Y2);
+    }
+    Fx = AXIS == 0 ? Fn : Ft;
+    Fy = AXIS == 0 ? Ft : Fn;
+  } else {
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+      const double vx = rtF * node<4, double>(i) + uF;
+      const double p = double(sm.F[i * G::NF + fi]) * vx;
+      Fr += p;
+      Fx += vx * p;
+      FE += 0.5 * vx * vx * p;
+    }
+#pragma unroll
+    for (int i = 0; i < QG; ++i)
+      FE += (rtF * node<3, double>(i) + uF) * double(sm.F[(QF + i) * G::NF + fi]);
   }
   int bad = 0;
   const double sc = a.lam * a.scale;
