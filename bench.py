@@ -29,6 +29,39 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # conserved-moment ledger.
 BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
 
+# Measured HBM bytes per launch of step_batch_kernel<2,float> on this workload
+# (2048^2): rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE in separate runs, scaled
+# by 2.0 and 1.0, the factors that make the same counters read 1 GiB for a
+# 1 GiB device copy (the counter summary kept with the profiles).
+# The figures belong to the kernel sources with the digest below; for any
+# other source the traffic is reported as null.
+KERNEL_SOURCES = ("paper_2302_00310_amd/csrc/pond_kernels.hip",
+                  "paper_2302_00310_amd/csrc/pond_internal.h")
+MEASURED_TRAFFIC = {
+    "sha256": "70101f1dfa205f3e53da6266f7833aad1b2af851b46d2586f13cb4a2c584cae9",
+    "n": 2048,
+    "fetch_bytes": 1.65963e9,
+    "write_bytes": 7.76725e8,
+}
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n: int):
+    """HBM bytes per launch from the recorded counters, or None when the
+    kernel sources or the grid differ from the ones they were taken on."""
+    m = MEASURED_TRAFFIC
+    if n != m["n"] or kernel_digest() != m["sha256"]:
+        return None
+    return m["fetch_bytes"] + m["write_bytes"]
+
 
 def flops_per_cell_2d(n_corr: int = 0) -> int:
     """Floating-point operations of one 2D cell-update as the kernel's
@@ -59,7 +92,7 @@ def parse():
     p.add_argument("--n", type=int, default=2048, help="grid side")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--serving-requests", type=int, default=64,
                    help="requests of the serving leg (0 skips it)")
     p.add_argument("--serving-sizes", type=str, default="128,256,512",
@@ -195,7 +228,7 @@ def main():
     achieved_tf = flops * cells / (kern_m * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
-                       "traffic": None, "kernel": "step_batch_kernel<2,float>",
+                       "traffic": measured_traffic(a.n), "kernel": "step_batch_kernel<2,float>",
                        "kernel_ms": kern_m, "flops_per_cell": flops}
     hbm = BYTES_PER_CELL["mixed"] * cells / (kern_m * 1e-3) / 1e9
     out["hbm_roofline"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
