@@ -67,8 +67,6 @@ int validate(const pond_config* c) {
       if (!(s[0] > 0.0) || !(s[3] > 0.0) || !std::isfinite(s[1]) || !std::isfinite(s[2]))
         return fail(POND_ERR_INVALID, "inflow state needs positive density and pressure");
     }
-  if (c->transform == POND_TF_GRAD)
-    return fail(POND_ERR_UNSUPPORTED, "the GPU step implements the Lagrange transform only");
   return POND_OK;
 }
 
@@ -277,6 +275,7 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   for (int k = 0; k < 4; ++k) a.bc[k] = c.bc[k];
   a.n_corr = c.n_corr;
   a.limiter = c.limiter;
+  a.transform = c.transform;
   if (twod) {
     a.tiles_x = (c.nx + kTX2 - 1) / kTX2;
     a.tiles_y = (c.ny + kTY2 - 1) / kTY2;
@@ -311,8 +310,8 @@ int pond_step(pond_state* s, int nsteps) {
   if (!s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
   for (int k = 0; k < nsteps; ++k) {
     if (s->cfg.dim == 2) {
-      POND_HIP(launch_step_batch(s->L.fp64, s->tab, 1, s->args.tiles_x * s->args.tiles_y, s->cur,
-                                 s->stream));
+      POND_HIP(launch_step_batch(s->L.fp64, 1u << s->cfg.transform, s->tab, 1,
+                                 s->args.tiles_x * s->args.tiles_y, s->cur, s->stream));
     } else {
       StepArgs a = s->args;
       a.n_in = s->n[s->cur];

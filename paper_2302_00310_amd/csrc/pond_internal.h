@@ -31,7 +31,7 @@ constexpr int kThreads = 256;
 struct StepArgs {
   int nx, ny;
   int bc[4];
-  int n_corr, limiter;
+  int n_corr, limiter, transform;  // transform: 0 Lagrange (App. B), 1 Grad projection
   int tiles_x, tiles_y;
   double inv_scale;        // 2^-E: fixed-point unit of the conserved-moment ledger
   double scale;            // 2^E
@@ -59,8 +59,10 @@ struct BatchEntry {
 };
 
 // Host-side launchers (defined in pond_kernels.hip).
-hipError_t launch_step_batch(bool fp64, const BatchEntry* tab, int n, int total_tiles, int parity,
-                             hipStream_t st);
+// tf_mask: bit t set launches the kernel of transform t (the batch may hold
+// solves with either transform; each kernel skips the other's blocks).
+hipError_t launch_step_batch(bool fp64, unsigned tf_mask, const BatchEntry* tab, int n,
+                             int total_tiles, int parity, hipStream_t st);
 hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
 hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,
                        size_t count, double scale, double cv, void* n, long long* U,

@@ -30,6 +30,7 @@ namespace {
 
 constexpr int BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1;
 constexpr int LIM_VANLEER = 0, LIM_MINMOD = 1;
+constexpr int TF_LAGRANGE = 0, TF_GRAD = 1;
 constexpr double kTieBand = 1e-11;  // |v_n| <= kTieBand sqrt(T_F): upwind tie
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
@@ -145,14 +146,16 @@ struct PairBasis {
   }
 };
 
-// Moment-matching map (App. B) of one lattice's populations from a frame
-// with (sqrt T, u) to the frame with (1/sqrt T', u'): on the tensor lattice
-// G = A_x (x) A_y with A[k][m] = l_k(xi_m), xi_m = s c_m + d, s = sqrt(T/T'),
-// d = (u - u')/sqrt(T'), applied factor by factor (transform_part below).
-template <int Q1, typename T, int AXIS, int K0, int NK>
-__device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* out);
+// Transform of one lattice's populations from a frame with (sqrt T, u) to the
+// frame with (1/sqrt T', u').  TF_LAGRANGE: the moment-matching map of App. B,
+// on the tensor lattice G = A_x (x) A_y with A[k][m] = l_k(xi_m),
+// xi_m = s c_m + d, s = sqrt(T/T'), d = (u - u')/sqrt(T'), applied factor by
+// factor.  TF_GRAD: Grad's projection (eq. GradsProjection).  In 1D the two
+// coincide.  The 2D maps are xform below.
+template <int TF, int Q1, typename T, int AXIS, int K0, int NK>
+__device__ __forceinline__ void xform(T s, T dn, T dt, const T* in, T* out);
 
-template <int D, int Q1, typename T>
+template <int D, int Q1, typename T, int TF>
 __device__ __forceinline__ void transform(double rt_src, double ux_src, double uy_src,
                                           double irt_dst, double ux_dst, double uy_dst,
                                           const T* in, T* out) {
@@ -164,7 +167,7 @@ __device__ __forceinline__ void transform(double rt_src, double ux_src, double u
     for (int m = 0; m < Q1; ++m) x[m] = s * node<Q1, T>(m) + dx;
     PairBasis<Q1, T>(x).template apply<1, 1>(in, out);
   } else {
-    transform_part<Q1, T, 0, 0, Q1>(s, dx, T((uy_src - uy_dst) * irt_dst), in, out);
+    xform<TF, Q1, T, 0, 0, Q1>(s, dx, T((uy_src - uy_dst) * irt_dst), in, out);
   }
 }
 
@@ -210,6 +213,97 @@ __device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* 
   const PairBasis<Q1, T> bn(xi);
 #pragma unroll
   for (int t = 0; t < NK; ++t) bn.template apply<1, 1>(Z[t], out + Q1 * t);
+}
+
+// He_a(c_k) / a! on the lattice nodes (probabilists' Hermite polynomials).
+template <int Q1>
+__host__ __device__ constexpr double hermite_node(int a, int k) {
+  const double c = node<Q1, double>(k);
+  return a == 0 ? 1.0 : a == 1 ? c : a == 2 ? (c * c - 1.0) / 2.0 : (c * c * c - 3.0 * c) / 6.0;
+}
+
+// Grad's projection of order K = Q1 - 1 into the target frame
+// (eq. GradsProjection; Hermite moments of App. A):
+//   f'_{kn,kt} = W_kn W_kt sum_{a + b <= K} alpha_ab He_a(c_kn) He_b(c_kt) / (a! b!),
+//   alpha_ab = sum_{mn,mt} He_a(x_mn) He_b(y_mt) f_{mn,mt},
+// with x = s c + dn (normal axis) and y = s c + dt (transverse axis); in and
+// out are indexed as in transform_part.  Keeping a + b <= K drops 6 of the 16
+// D2Q16 modes and 3 of the 9 D2Q9 ones, so this map is not the identity when
+// the frames coincide.
+template <int Q1, typename T, int AXIS>
+__device__ __forceinline__ void transform_grad(T s, T dn, T dt, const T* in, T* out) {
+  constexpr int K = Q1 - 1;
+  constexpr int SN = AXIS == 0 ? 1 : Q1, ST = AXIS == 0 ? Q1 : 1;
+  auto herm = [](T x, T (&h)[Q1]) {  // He_0..He_K at x
+    const T x2 = x * x;
+    h[0] = T(1);
+    h[1] = x;
+    h[2] = x2 - T(1);
+    if constexpr (Q1 == 4) h[3] = x * (x2 - T(3));
+  };
+  // beta[mn][b] = sum_mt He_b(y_mt) f[mn][mt], accumulated point by point so
+  // that only one point's Hermite values are live
+  T beta[Q1][Q1];
+#pragma unroll
+  for (int mt = 0; mt < Q1; ++mt) {
+    T h[Q1];
+    herm(s * node<Q1, T>(mt) + dt, h);
+#pragma unroll
+    for (int mn = 0; mn < Q1; ++mn) {
+      const T f = in[mn * SN + mt * ST];
+#pragma unroll
+      for (int b = 0; b <= K; ++b) beta[mn][b] = mt == 0 ? h[b] * f : beta[mn][b] + h[b] * f;
+    }
+  }
+  // alpha[a][b] = sum_mn He_a(x_mn) beta[mn][b], a + b <= K
+  T alpha[Q1][Q1];
+#pragma unroll
+  for (int mn = 0; mn < Q1; ++mn) {
+    T h[Q1];
+    herm(s * node<Q1, T>(mn) + dn, h);
+#pragma unroll
+    for (int b = 0; b <= K; ++b) {
+#pragma unroll
+      for (int a = 0; a + b <= K; ++a)
+        alpha[a][b] = mn == 0 ? h[a] * beta[0][b] : alpha[a][b] + h[a] * beta[mn][b];
+    }
+  }
+  // gamma[kn][b] = W_kn sum_{a <= K - b} He_a(c_kn)/a! alpha[a][b];
+  // out[kn][kt] = W_kt sum_b He_b(c_kt)/b! gamma[kn][b]
+#pragma unroll
+  for (int kn = 0; kn < Q1; ++kn) {
+    T gam[Q1];
+#pragma unroll
+    for (int b = 0; b <= K; ++b) {
+      T acc = T(hermite_node<Q1>(0, kn)) * alpha[0][b];
+#pragma unroll
+      for (int a = 1; a + b <= K; ++a) acc += T(hermite_node<Q1>(a, kn)) * alpha[a][b];
+      gam[b] = T(weight<Q1, double>(kn)) * acc;
+    }
+#pragma unroll
+    for (int kt = 0; kt < Q1; ++kt) {
+      T acc = gam[0];
+#pragma unroll
+      for (int b = 1; b <= K; ++b) acc += T(hermite_node<Q1>(b, kt)) * gam[b];
+      out[kn + Q1 * kt] = T(weight<Q1, double>(kt)) * acc;
+    }
+  }
+}
+
+template <int TF, int Q1, typename T, int AXIS, int K0, int NK>
+__device__ __forceinline__ void xform(T s, T dn, T dt, const T* in, T* out) {
+  if constexpr (TF == TF_GRAD) {
+    if constexpr (NK == Q1) {
+      transform_grad<Q1, T, AXIS>(s, dn, dt, in, out);
+    } else {
+      T all[Q1 * Q1];
+      transform_grad<Q1, T, AXIS>(s, dn, dt, in, all);
+#pragma unroll
+      for (int j = 0; j < Q1 * NK; ++j) out[j] = all[j + Q1 * K0];
+    }
+  } else {
+    transform_part<Q1, T, AXIS, K0, NK>(s, dn, dt, in, out);
+  }
 }
 
 // Quadrature of the Lagrange basis against the weights:
@@ -467,7 +561,7 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
 // operands of the two limiters are selected per population, so each
 // population costs one normal and one transverse limiter; ties take a second
 // pass.
-template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM>
+template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM, int TF>
 __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>& sm,
                                             const int (&st)[Geo<D>::NS], int plane0, double rtF,
                                             double irtF, double uF, double vF, T* bar) {
@@ -487,9 +581,9 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
       const T s = T(sm.RT[h] * irtF);
       const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
       const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
-      transform_part<Q1, T, AXIS, K0, NK>(s, dn, dt, in, out);
+      xform<TF, Q1, T, AXIS, K0, NK>(s, dn, dt, in, out);
     } else {
-      transform<1, Q1, T>(sm.RT[h], sm.U[h], 0.0, irtF, uF, 0.0, in, out);
+      transform<1, Q1, T, TF>(sm.RT[h], sm.U[h], 0.0, irtF, uF, 0.0, in, out);
     }
     // keep the scheduler from overlapping the stencil cells' transforms
     // (each one holds its own LDS loads and coefficients in registers)
@@ -592,7 +686,7 @@ __device__ __forceinline__ bool tied(double rtF, double uF, double vF) {
 // running limiter operands, so the frame-dependent coefficients of a cell are
 // formed once per face rather than once per transverse row.  Faces where a
 // population's normal velocity falls in the tie band take the row-wise path.
-template <int Q1, typename T, int AXIS, int LIM>
+template <int Q1, typename T, int AXIS, int LIM, int TF>
 __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& sm,
                                                  const int (&st)[Geo<2>::NS], int plane0,
                                                  int fidx, double rtF, double irtF, double uF,
@@ -611,7 +705,7 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
     const T s = T(sm.RT[h] * irtF);
     const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
     const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
-    transform_part<Q1, T, AXIS, 0, Q1>(s, dn, dt, in, o);
+    xform<TF, Q1, T, AXIS, 0, Q1>(s, dn, dt, in, o);
     // the empty asm pins the finished outputs: without it the compiler sinks
     // parts of the transform into the consumers and keeps its operands live
     // across the next cells (spills)
@@ -671,7 +765,7 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
   for (int j = 0; j < Q; ++j) out[j] = park(j) + S[j];
 }
 
-template <int D, typename T, int AXIS, int LIM>
+template <int D, typename T, int AXIS, int LIM, int TF>
 __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG;
@@ -681,11 +775,11 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
   // eq. AvgFrame
   double uF = 0.5 * (sm.U[hL] + sm.U[hR]);
   double vF = D == 2 ? 0.5 * (sm.V[hL] + sm.V[hR]) : 0.0;
-  double TF = 0.5 * (sm.RT[hL] * sm.RT[hL] + sm.RT[hR] * sm.RT[hR]);
+  double TFc = 0.5 * (sm.RT[hL] * sm.RT[hL] + sm.RT[hR] * sm.RT[hR]);  // face temperature
   double rho_b = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0, rtF = 0.0, irtF = 0.0;
 #pragma unroll 1
   for (int pass = 0; pass <= a.n_corr; ++pass) {
-    rtF = sqrt(TF);
+    rtF = sqrt(TFc);
     irtF = 1.0 / rtF;
     // macroscopic fields at the face, in FP64; f-bar is parked in the face
     // slot of LDS while g is reconstructed
@@ -708,7 +802,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
     if constexpr (D == 2) {
       if (kWhole && !tied<4, AXIS>(rtF, uF, vF)) {
         T bar[QF];
-        reconstruct_full<4, T, AXIS, LIM>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
+        reconstruct_full<4, T, AXIS, LIM, TF>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
         // moments through row sums R_n (over t) and column sums C_t (over n)
         const double un = AXIS == 0 ? uF : vF, ut = AXIS == 0 ? vF : uF;
         double C[4] = {0.0, 0.0, 0.0, 0.0}, mn = 0.0, mt = 0.0, e2 = 0.0;
@@ -741,20 +835,20 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
         static_for<0, 4>([&](auto part) {
           constexpr int K0 = decltype(part)::value;
           T bar[4];
-          reconstruct<D, 4, T, AXIS, K0, 1, LIM>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+          reconstruct<D, 4, T, AXIS, K0, 1, LIM, TF>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
           take_f(bar, K0, 1);
         });
       }
     } else {
       T bar[4];
-      reconstruct<D, 4, T, AXIS, 0, 1, LIM>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+      reconstruct<D, 4, T, AXIS, 0, 1, LIM, TF>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
       take_f(bar, 0, 1);
     }
     auto g_rows = [&]() {
       static_for<0, (D == 2 ? 3 : 1)>([&](auto part) {
         constexpr int K0 = decltype(part)::value;
         T gbar[3];
-        reconstruct<D, 3, T, AXIS, K0, 1, LIM>(a, sm, st, QF, rtF, irtF, uF, vF, gbar);
+        reconstruct<D, 3, T, AXIS, K0, 1, LIM, TF>(a, sm, st, QF, rtF, irtF, uF, vF, gbar);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           const int i = D == 1 ? j : (AXIS == 0 ? j + 3 * K0 : K0 + 3 * j);
@@ -766,7 +860,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
     if constexpr (D == 2) {
       if (kWhole && !tied<3, AXIS>(rtF, uF, vF)) {
         T gbar[QG];
-        reconstruct_full<3, T, AXIS, LIM>(a, sm, st, QF, fidx, rtF, irtF, uF, vF, gbar);
+        reconstruct_full<3, T, AXIS, LIM, TF>(a, sm, st, QF, fidx, rtF, irtF, uF, vF, gbar);
 #pragma unroll
         for (int j = 0; j < QG; ++j) {
           const int n = j % 3, t = j / 3;
@@ -787,35 +881,67 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
     if (pass < a.n_corr) {  // corrector: re-evaluate in the frame just found
       uF = ub;
       vF = vb;
-      TF = Tb;
+      TFc = Tb;
     }
   }
   // face equilibrium rho G_{u_b,T_b}^{lambda_F} W (eq. NonComovingEq), separable;
   // phi = c1 phi-bar + c2 phi^eq inverts eq. FluxTransf
   const T sb = T(sqrt(Tb) * irtF);
   const T c1 = T(a.c_face1), c2 = T(a.c_face2);
-  {
-    T ex[4], ey[4];
-    eq_factor<4, T>(sb, T((ub - uF) * irtF), ex);
-    if constexpr (D == 2) eq_factor<4, T>(sb, T((vb - vF) * irtF), ey);
-    const T r = T(rho_b);
+  if constexpr (D == 2 && TF == TF_GRAD) {
+    // not separable: the map applied to the comoving rho W (and g's)
+    const T dn = T(((AXIS == 0 ? ub : vb) - (AXIS == 0 ? uF : vF)) * irtF);
+    const T dt = T(((AXIS == 0 ? vb : ub) - (AXIS == 0 ? vF : uF)) * irtF);
+    {
+      T w[QF], eq[QF];
+      const T r = T(rho_b);
 #pragma unroll
-    for (int i = 0; i < QF; ++i) {
-      const T feq = D == 2 ? r * ex[i & 3] * ey[i >> 2] : r * ex[i];
-      T& slot = sm.F[i * G::NF + fidx];
-      slot = c1 * slot + c2 * feq;
+      for (int i = 0; i < QF; ++i) w[i] = r * wf<D, T>(i);
+      transform_grad<4, T, AXIS>(sb, dn, dt, w, eq);
+#pragma unroll
+      for (int j = 0; j < QF; ++j) {
+        const int n = j % 4, t = j / 4;
+        T& slot = sm.F[(AXIS == 0 ? n + 4 * t : t + 4 * n) * G::NF + fidx];
+        slot = c1 * slot + c2 * eq[j];
+      }
     }
-  }
-  {
-    T ex[3], ey[3];
-    eq_factor<3, T>(sb, T((ub - uF) * irtF), ex);
-    if constexpr (D == 2) eq_factor<3, T>(sb, T((vb - vF) * irtF), ey);
-    const T r = T(a.geq * Tb * rho_b);
+    {
+      T w[QG], eq[QG];
+      const T r = T(a.geq * Tb * rho_b);
 #pragma unroll
-    for (int i = 0; i < QG; ++i) {
-      const T geq = D == 2 ? r * ex[i % 3] * ey[i / 3] : r * ex[i];
-      T& slot = sm.F[(QF + i) * G::NF + fidx];
-      slot = c1 * slot + c2 * geq;
+      for (int i = 0; i < QG; ++i) w[i] = r * wg<D, T>(i);
+      transform_grad<3, T, AXIS>(sb, dn, dt, w, eq);
+#pragma unroll
+      for (int j = 0; j < QG; ++j) {
+        const int n = j % 3, t = j / 3;
+        T& slot = sm.F[(QF + (AXIS == 0 ? n + 3 * t : t + 3 * n)) * G::NF + fidx];
+        slot = c1 * slot + c2 * eq[j];
+      }
+    }
+  } else {
+    {
+      T ex[4], ey[4];
+      eq_factor<4, T>(sb, T((ub - uF) * irtF), ex);
+      if constexpr (D == 2) eq_factor<4, T>(sb, T((vb - vF) * irtF), ey);
+      const T r = T(rho_b);
+#pragma unroll
+      for (int i = 0; i < QF; ++i) {
+        const T feq = D == 2 ? r * ex[i & 3] * ey[i >> 2] : r * ex[i];
+        T& slot = sm.F[i * G::NF + fidx];
+        slot = c1 * slot + c2 * feq;
+      }
+    }
+    {
+      T ex[3], ey[3];
+      eq_factor<3, T>(sb, T((ub - uF) * irtF), ex);
+      if constexpr (D == 2) eq_factor<3, T>(sb, T((vb - vF) * irtF), ey);
+      const T r = T(a.geq * Tb * rho_b);
+#pragma unroll
+      for (int i = 0; i < QG; ++i) {
+        const T geq = D == 2 ? r * ex[i % 3] * ey[i / 3] : r * ex[i];
+        T& slot = sm.F[(QF + i) * G::NF + fidx];
+        slot = c1 * slot + c2 * geq;
+      }
     }
   }
   if (!(rho_b > 0.0) || !(Tb > 0.0)) atomicOr(a.flag, 1);
@@ -897,7 +1023,7 @@ __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& s
 
 // Flux of two opposite faces into the cell frame (eq. fluxEq):
 // acc += v_a^{lambda_j} (G phi_hi - G phi_lo).
-template <int D, typename T, int AXIS>
+template <int D, typename T, int AXIS, int TF>
 __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, const Frame& c,
                                              T (&acc)[Geo<D>::NP]) {
   using G = Geo<D>;
@@ -910,14 +1036,14 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
     T in[QF], out[QF];
 #pragma unroll
     for (int i = 0; i < QF; ++i) in[i] = sm.F[i * G::NF + fi];
-    transform<D, 4, T>(rtF, uF, vF, c.irt, c.ux, c.uy, in, out);
+    transform<D, 4, T, TF>(rtF, uF, vF, c.irt, c.ux, c.uy, in, out);
 #pragma unroll
     for (int i = 0; i < QF; ++i) dlt[i] = side ? out[i] - dlt[i] : out[i];
     __builtin_amdgcn_sched_barrier(0);
     T ing[QG], outg[QG];
 #pragma unroll
     for (int i = 0; i < QG; ++i) ing[i] = sm.F[(QF + i) * G::NF + fi];
-    transform<D, 3, T>(rtF, uF, vF, c.irt, c.ux, c.uy, ing, outg);
+    transform<D, 3, T, TF>(rtF, uF, vF, c.irt, c.ux, c.uy, ing, outg);
 #pragma unroll
     for (int i = 0; i < QG; ++i) dlt[QF + i] = side ? outg[i] - dlt[QF + i] : outg[i];
     __builtin_amdgcn_sched_barrier(0);
@@ -938,7 +1064,7 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
 // --------------------------------------------------------------------------
 // The fused step kernel.
 // --------------------------------------------------------------------------
-template <int D, typename T, int LIM>
+template <int D, typename T, int LIM, int TF>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
@@ -1000,7 +1126,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       st[6] = hL + 1 + G::HX;
       st[7] = hL + 1 - G::HX;
     }
-    face_eval<D, T, 0, LIM>(a, sm, st, tid);
+    face_eval<D, T, 0, LIM, TF>(a, sm, st, tid);
   }
   __syncthreads();
   // ---- 2. west/east faces into the cell frame
@@ -1010,7 +1136,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
   long long dU[4] = {0, 0, 0, 0};
   if (tid < G::NI) {
     const int fw = cx + (G::TX + 1) * cy;
-    gather_faces<D, T, 0>(sm, fw, fw + 1, own_frame(), acc);
+    gather_faces<D, T, 0, TF>(sm, fw, fw + 1, own_frame(), acc);
     long long pw[4], pe[4];
     __builtin_amdgcn_sched_barrier(0);
     face_flux<D, T, 0>(a, sm, fw, pw);
@@ -1042,7 +1168,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       st[5] = hS - 1;
       st[6] = hS + G::HX + 1;
       st[7] = hS + G::HX - 1;
-      face_eval<D, T, 1, LIM>(a, sm, st, tid);
+      face_eval<D, T, 1, LIM, TF>(a, sm, st, tid);
     }
     __syncthreads();
     // ---- 4. south/north faces
@@ -1052,7 +1178,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     }
     if (tid < G::NI) {
       const int fs = cx + G::TX * cy;
-      gather_faces<D, T, 1>(sm, fs, fs + G::TX, own_frame(), acc);
+      gather_faces<D, T, 1, TF>(sm, fs, fs + G::TX, own_frame(), acc);
       long long ps[4], pn[4];
       __builtin_amdgcn_sched_barrier(0);
       face_flux<D, T, 1>(a, sm, fs, ps);
@@ -1083,9 +1209,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     const Frame nf = gauge(U2, a);
     T n2[NP];
     __builtin_amdgcn_sched_barrier(0);
-    transform<D, 4, T>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
+    transform<D, 4, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
     __builtin_amdgcn_sched_barrier(0);
-    transform<D, 3, T>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, gt, n2 + QF);
+    transform<D, 3, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, gt, n2 + QF);
     __builtin_amdgcn_sched_barrier(0);
     const T r2 = T(nf.rho), rg2 = T(a.geq * nf.T * nf.rho);
 #pragma unroll
@@ -1112,8 +1238,9 @@ template <int D, typename T>
 __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1) step_kernel(StepArgs a) {
   __shared__ Smem<D, T> sm;
   // the limiter is uniform over a launch: one straight-line body per kind
-  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD>(a, blockIdx.x, sm);
-  else step_tile<D, T, LIM_VANLEER>(a, blockIdx.x, sm);
+  // (in 1D both transforms are the same map)
+  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD, TF_LAGRANGE>(a, blockIdx.x, sm);
+  else step_tile<D, T, LIM_VANLEER, TF_LAGRANGE>(a, blockIdx.x, sm);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin (block b to XCD b mod 8),
@@ -1130,7 +1257,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // A ragged batch of independent solves in one launch: block b advances tile
 // b - tile_begin of the entry whose tile range holds b.  Each entry carries
 // the arguments of both step parities; step `parity` uses args[parity].
-template <int D, typename T>
+template <int D, typename T, int TF>
 __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
     step_batch_kernel(const BatchEntry* tab, int n, int parity) {
   __shared__ Smem<D, T> sm;
@@ -1143,9 +1270,12 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
   // copied before the first store, so the uniform loads stay scalar
   const StepArgs a = tab[lo].args[parity];
   const int tile = b - tab[lo].tile_begin;
+  // one kernel per transform (each keeps its own register allocation);
+  // blocks of solves that use the other transform leave at once
+  if (a.transform != TF) return;
   // the limiter is uniform over a solve: one straight-line body per kind
-  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD>(a, tile, sm);
-  else step_tile<D, T, LIM_VANLEER>(a, tile, sm);
+  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD, TF>(a, tile, sm);
+  else step_tile<D, T, LIM_VANLEER, TF>(a, tile, sm);
 }
 
 // --------------------------------------------------------------------------
@@ -1242,11 +1372,17 @@ hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_step_batch(bool fp64, const BatchEntry* tab, int n, int total_tiles, int parity,
-                             hipStream_t st) {
+hipError_t launch_step_batch(bool fp64, unsigned tf_mask, const BatchEntry* tab, int n,
+                             int total_tiles, int parity, hipStream_t st) {
   const dim3 grid(total_tiles), block(kThreads);
-  if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double>), grid, block, 0, st, tab, n, parity);
-  else hipLaunchKernelGGL((step_batch_kernel<2, float>), grid, block, 0, st, tab, n, parity);
+  if (tf_mask & (1u << TF_LAGRANGE)) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_LAGRANGE>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_LAGRANGE>), grid, block, 0, st, tab, n, parity);
+  }
+  if (tf_mask & (1u << TF_GRAD)) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD>), grid, block, 0, st, tab, n, parity);
+  }
   return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ struct pond_server {
   // graph cache for the current resident set: key = (K, parity of the first step)
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   int n_tab = 0, total_tiles = 0, phase = 0;
+  unsigned tf_mask = 0;  // transforms present in the resident set (bit per transform)
   int device = 0;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
@@ -150,6 +151,8 @@ int upload_table(pond_server* S) {
   }
   S->n_tab = int(S->active.size());
   S->total_tiles = tile;
+  S->tf_mask = 0;
+  for (Job* j : S->active) S->tf_mask |= 1u << j->cfg.transform;
   S->phase = 0;
   hipError_t err = hipMemcpyAsync(S->dev_tab, S->host_tab, sizeof(BatchEntry) * S->n_tab,
                                   hipMemcpyHostToDevice, S->stream);
@@ -166,7 +169,8 @@ int run_steps(pond_server* S, int K) {
     hipError_t err = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
     for (int j = 0; j < K; ++j)
-      launch_step_batch(false, S->dev_tab, S->n_tab, S->total_tiles, (par0 + j) & 1, S->stream);
+      launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab, S->total_tiles, (par0 + j) & 1,
+                        S->stream);
     hipGraph_t g = nullptr;
     err = hipStreamEndCapture(S->stream, &g);
     if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");

@@ -78,10 +78,10 @@ def test_half_periodic_axis_is_rejected(pond):
     assert pond.pond_state_bytes(c) == 0
 
 
-def test_grad_transform_reports_unsupported(pond):
-    c = _cfg(pond, transform=1)
-    h = C.c_void_p()
-    assert pond.load_library().pond_create(C.byref(c), None, 0, None, C.byref(h)) == -6
+def test_grad_transform_is_accepted_and_unknown_rejected(pond):
+    grad, lag = _cfg(pond, transform=1), _cfg(pond, transform=0)
+    assert pond.pond_state_bytes(grad) == pond.pond_state_bytes(lag) > 0
+    assert pond.pond_state_bytes(_cfg(pond, transform=7)) == 0
 
 
 def test_state_bytes_scale_with_precision(pond):

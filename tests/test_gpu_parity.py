@@ -50,7 +50,9 @@ def test_sod_1d_fp64_every_step():
     print("sod_1d worst", worst)
 
 
-@pytest.mark.parametrize("case", ["vortex", "quadrants", "shu_osher", "vortex_ncorr", "quadrants_minmod"])
+@pytest.mark.parametrize("case", ["vortex", "quadrants", "shu_osher", "vortex_ncorr", "quadrants_minmod",
+                                  "vortex_grad", "quadrants_grad", "shu_osher_grad",
+                                  "quadrants_minmod_grad"])
 def test_2d_fp64_small_grids(case):
     if case.startswith("vortex"):
         wl = inputs.vortex_2d(48, steps=1, noise=1e-3, ny=40)
@@ -61,8 +63,10 @@ def test_2d_fp64_small_grids(case):
     kw = {}
     if case.endswith("ncorr"):
         kw["n_corr"] = 2
-    if case.endswith("minmod"):
+    if "minmod" in case:
         kw["limiter"] = 1
+    if case.endswith("grad"):
+        kw["transform"] = 1  # Grad's projection instead of the Lagrange map
     s = solver(wl, FP64, **kw)
     o = oracle.Oracle(wl, **kw)
     for _ in range(4):
@@ -73,16 +77,17 @@ def test_2d_fp64_small_grids(case):
     assert _pops_err(s, o) <= 1e-12
 
 
-@pytest.mark.parametrize("case", ["vortex", "quadrants", "shu_osher"])
+@pytest.mark.parametrize("case", ["vortex", "quadrants", "shu_osher", "vortex_grad", "quadrants_grad"])
 def test_2d_mixed_small_grids(case):
-    if case == "vortex":
+    if case.startswith("vortex"):
         wl = inputs.vortex_2d(48, steps=1, noise=1e-3, ny=40)
-    elif case == "quadrants":
+    elif case.startswith("quadrants"):
         wl = inputs.quadrants_2d(35, steps=1, seed=3, ny=33)
     else:
         wl = inputs.shu_osher_2d(64, 20, steps=1)
-    s = solver(wl, MIXED)
-    o = oracle.Oracle(wl)
+    kw = {"transform": 1} if case.endswith("grad") else {}
+    s = solver(wl, MIXED, **kw)
+    o = oracle.Oracle(wl, **kw)
     s.step(60)
     o.step(60)
     e = moment_errors(s.moments(), o.moments(), l2=True)

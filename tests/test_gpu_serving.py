@@ -31,22 +31,23 @@ def _mix():
     ]
 
 
-def _alone(pond, wl, steps):
-    s = pond.Solver(wl, precision=pond.POND_MIXED)
+def _alone(pond, wl, steps, transform=0):
+    s = pond.Solver(wl, precision=pond.POND_MIXED, transform=transform)
     s.step(steps)
     m = s.moments()
     s.close()
     return [a.reshape(-1) for a in m]
 
 
-def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0):
+def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0, transforms=None):
     import torch
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     srv = pond.pond_server_create(arena.data_ptr(), arena_bytes, 0, max_active)
     ids = []
     try:
         for k, (wl, steps) in enumerate(jobs):
-            cfg = pond.make_config(wl, precision=pond.POND_MIXED)
+            cfg = pond.make_config(wl, precision=pond.POND_MIXED,
+                                   transform=transforms[k] if transforms else 0)
             ids.append(pond.pond_submit(srv, cfg, *wl.fields(), steps, tag=k))
         out = {}
         t_end = time.time() + timeout
@@ -123,3 +124,17 @@ def test_a_failing_solve_does_not_touch_the_others(pond):
         assert got[k][0] == pond.POND_OK
         for a, b in zip(got[k][1], _alone(pond, wl, steps)):
             assert np.array_equal(a, b)
+
+
+def test_lagrange_and_grad_solves_share_a_batch(pond):
+    """Solves with either transform resident together (one kernel per
+    transform over the same batch table); each result equals its solve
+    alone."""
+    jobs = _mix()[:4]
+    transforms = [1, 0, 1, 0]
+    got = _serve(pond, jobs, 1 << 30, transforms=transforms)
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, _ = got[k]
+        assert rc == pond.POND_OK
+        for a, b in zip(m, _alone(pond, wl, steps, transforms[k])):
+            assert np.array_equal(a, b), k
