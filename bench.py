@@ -184,6 +184,7 @@ def serving_leg(n_req, sizes, arena_gb, max_active):
                 rc, _, times = pond.pond_poll(srv, rid, wl.nx * wl.ny)
                 if rc != pond.POND_PENDING:
                     results[j] = (rc, times)
+                    print(f"serving: {len(results)}/{len(reqs)} done", file=sys.stderr, flush=True)
             time.sleep(0.001)
         makespan = time.perf_counter() - t0
     finally:
@@ -191,7 +192,10 @@ def serving_leg(n_req, sizes, arena_gb, max_active):
     lat = np.array([r[1]["t_done"] - r[1]["t_submit"] for r in results.values()])
     queue = np.array([r[1]["t_admit"] - r[1]["t_submit"] for r in results.values()])
     serv = np.array([r[1]["t_done"] - r[1]["t_admit"] for r in results.values()])
+    failed = [[j, int(r[0]), reqs[j].workload.nx, reqs[j].workload.name]
+              for j, r in sorted(results.items()) if r[0] != 0]
     return {"requests": len(reqs), "ok": int(sum(1 for r in results.values() if r[0] == 0)),
+            "failed": failed,
             "sizes": list(sizes), "rate_per_s": 50.0, "arena_gb": arena_gb,
             "max_active": max_active, "policy": "FCFS with memory admission",
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
@@ -228,7 +232,7 @@ def main():
     achieved_tf = flops * cells / (kern_m * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
-                       "traffic": measured_traffic(a.n), "kernel": "step_batch_kernel<2,float>",
+                       "traffic": measured_traffic(a.n), "kernel": "step_batch_kernel<2,float,0>",
                        "kernel_ms": kern_m, "flops_per_cell": flops}
     hbm = BYTES_PER_CELL["mixed"] * cells / (kern_m * 1e-3) / 1e9
     out["hbm_roofline"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -138,3 +138,34 @@ def test_lagrange_and_grad_solves_share_a_batch(pond):
         assert rc == pond.POND_OK
         for a, b in zip(m, _alone(pond, wl, steps, transforms[k])):
             assert np.array_equal(a, b), k
+
+
+def test_input_outside_the_methods_range_is_reported(pond):
+    """Request 456 of the 512-solve serving stream (128^2 quadrants, Mach cap
+    3.4): across the left half of the horizontal interface the two quadrants
+    move apart at 2.4 (in units where the thermal speed is ~0.65), so the
+    face-frame transforms reach far outside the node range.  The FP64 oracle
+    turns the two rows at the interface non-finite on its first step; the
+    GPU step reports POND_ERR_UNSTABLE for the same input, alone and as a
+    served request."""
+    import oracle
+    reqs = inputs.serving_requests(512, sizes=(128, 256, 512, 1024, 2048), materialize=False)
+    w = reqs[456].workload
+    sub = inputs._rng(5 * 1000 + 456)
+    n = int(sub.choice(np.array((128, 256, 512, 1024, 2048))))
+    mach = float(sub.uniform(0.5, 4.0))
+    wl = inputs.quadrants_2d(n, w.steps, seed=w.seed, tau=w.tau, prandtl=w.prandtl, mach_cap=mach)
+    o = oracle.Oracle(wl)
+    o.step(1)
+    bad = ~np.isfinite(o.moments()[0])
+    assert set(np.nonzero(bad)[0]) == {63, 64}
+    s = pond.Solver(wl, precision=pond.POND_MIXED)
+    try:
+        s.step(1)
+        with pytest.raises(pond.PondError) as e:
+            s.moments()
+        assert e.value.code == -4
+    finally:
+        s.close()
+    got = _serve(pond, [(wl, 20)], 1 << 28)
+    assert got[0][0] == -4
