@@ -38,8 +38,8 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 int validate(const pond_config* c) {
   if (!c) return fail(POND_ERR_INVALID, "null config");
   if (c->dim != 1 && c->dim != 2) return fail(POND_ERR_INVALID, "dim must be 1 or 2");
-  if (c->nx < 1 || c->ny < 1 || (c->dim == 1 && c->ny != 1))
-    return fail(POND_ERR_INVALID, "grid needs nx >= 1, ny >= 1 (ny = 1 in 1D)");
+  if (c->nx < 4 || (c->dim == 2 && c->ny < 4) || (c->dim == 1 && c->ny != 1))
+    return fail(POND_ERR_INVALID, "grid needs nx >= 4 and, in 2D, ny >= 4 (ny = 1 in 1D)");
   if ((c->dim == 1 && c->lattice != POND_D1Q4) || (c->dim == 2 && c->lattice != POND_D2Q16))
     return fail(POND_ERR_INVALID, "lattice must be D1Q4 in 1D and D2Q16 in 2D");
   if (c->precision != POND_FP64 && c->precision != POND_MIXED)

@@ -59,7 +59,8 @@ def _cfg(pond, **over):
     return c
 
 
-@pytest.mark.parametrize("field,value", [("dim", 3), ("nx", 0), ("gamma", 1.0), ("tau", 0.0),
+@pytest.mark.parametrize("field,value", [("dim", 3), ("nx", 0), ("nx", 3), ("ny", 3),
+                                         ("gamma", 1.0), ("tau", 0.0),
                                          ("prandtl", 1.5), ("prandtl", 0.0), ("cfl", -1.0),
                                          ("n_corr", 9), ("limiter", 7), ("precision", 5),
                                          ("lattice", 1)])

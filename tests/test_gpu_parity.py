@@ -208,3 +208,24 @@ def test_full_size_sampled_cells(name, precision):
     else:
         for k in range(4):
             assert rel_l2(got[:, k], ref[:, k]) <= 1e-5 or np.max(np.abs(got[:, k] - ref[:, k])) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+@pytest.mark.parametrize("case", ["periodic_4x4", "zero_gradient_4x5", "inflow_6x4", "sod_4"])
+def test_smallest_grids(case, precision):
+    """The smallest accepted grids (4 cells a side): one tile, every cell
+    next to a boundary, ghost layers as deep as half the grid."""
+    if case == "periodic_4x4":
+        wl = inputs.vortex_2d(4, steps=1, noise=1e-3)
+    elif case == "zero_gradient_4x5":
+        wl = inputs.quadrants_2d(4, steps=1, seed=7, ny=5)
+    elif case == "inflow_6x4":
+        wl = inputs.shu_osher_2d(6, 4, steps=1)
+    else:
+        wl = inputs.sod_1d(4, 1)
+    s = solver(wl, precision)
+    o = oracle.Oracle(wl)
+    s.step(10)
+    o.step(10)
+    e = moment_errors(s.moments(), o.moments(), l2=precision == MIXED)
+    assert max(e.values()) <= (1e-12 if precision == FP64 else 1e-5), e
