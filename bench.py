@@ -187,6 +187,7 @@ def serving_leg(n_req, sizes, arena_gb, max_active):
                     print(f"serving: {len(results)}/{len(reqs)} done", file=sys.stderr, flush=True)
             time.sleep(0.001)
         makespan = time.perf_counter() - t0
+        stats = pond.pond_server_stats(srv)
     finally:
         pond.pond_server_destroy(srv)
     lat = np.array([r[1]["t_done"] - r[1]["t_submit"] for r in results.values()])
@@ -201,7 +202,8 @@ def serving_leg(n_req, sizes, arena_gb, max_active):
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "queue_p50_s": float(np.percentile(queue, 50)), "queue_p99_s": float(np.percentile(queue, 99)),
             "service_p50_s": float(np.percentile(serv, 50)), "service_p99_s": float(np.percentile(serv, 99)),
-            "throughput_cell_updates_per_s": cells_steps / makespan, "makespan_s": makespan}
+            "throughput_cell_updates_per_s": cells_steps / makespan, "makespan_s": makespan,
+            "server": stats}
 
 
 def main():

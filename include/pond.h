@@ -180,6 +180,15 @@ int pond_submit(pond_server* srv, const pond_request* req, uint64_t* id);
    moments into res' arrays, fills the times and returns the solve's status
    (once: the result is released after a non-pending poll). */
 int pond_poll(pond_server* srv, uint64_t id, pond_result* res);
+/* Counters since pond_server_create (seconds on the server's clock):
+   out[0] elapsed, out[1] cell-updates advanced, out[2] batched chunks
+   launched, out[3] changes of the resident set, and host time spent in
+   out[4] admissions (state set-up and initial fields), out[5] retirements
+   (moments to host, including the wait for the GPU), out[6] batch-table
+   uploads, out[7] graph captures; out[8] GPU time of the step chunks
+   finished so far (HIP events around each chunk).  Serving metrics only;
+   not on the step path. */
+int pond_server_stats(pond_server* srv, double out[9]);
 /* Stops admitting, finishes or drops queued work, joins the thread. */
 int pond_server_destroy(pond_server* srv);
 

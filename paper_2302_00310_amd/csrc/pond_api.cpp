@@ -490,6 +490,8 @@ int pond_load(pond_state* s, const char* path) {
   s->cur = 0;
   POND_HIP(hipMemcpy(s->n[0], buf.data(), h.pop_bytes, hipMemcpyHostToDevice));
   POND_HIP(hipMemcpy(s->U[0], buf.data() + h.pop_bytes, h.led_bytes, hipMemcpyHostToDevice));
+  const int zero = 0;  // a checkpoint holds a healthy state: clear the status flag
+  POND_HIP(hipMemcpy(s->flag, &zero, sizeof(int), hipMemcpyHostToDevice));
   return upload_table(s);
 }
 

@@ -475,7 +475,16 @@ struct Smem {
   double U[G::NH], V[G::NH], RT[G::NH];  // cell frames (u_x, u_y, sqrt T)
   T F[G::NP * G::NF];          // face populations phi^{lambda_F}
   double FU[G::NF], FV[G::NF], FRT[G::NF];          // face frames
+  int skip;                    // the solve has already failed: leave the tile
 };
+
+// Sets `bit` in the solve's status flag if `cond` holds on any active lane of
+// the wave, with one atomic per wave: a solve that has gone non-physical
+// would otherwise have every cell contend for the one flag word.
+__device__ __forceinline__ void raise_flag(int* flag, bool cond, int bit) {
+  const unsigned long long m = __ballot(cond);
+  if (m && __lane_id() == __ffsll((long long)m) - 1) atomicOr(flag, bit);
+}
 
 // Halo coordinates of tile slot k: interior slots first (thread k owns
 // interior slot k), then the ring.
@@ -944,7 +953,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
       }
     }
   }
-  if (!(rho_b > 0.0) || !(Tb > 0.0)) atomicOr(a.flag, 1);
+  raise_flag(a.flag, !(rho_b > 0.0) || !(Tb > 0.0), 1);
   sm.FU[fidx] = uF;
   sm.FV[fidx] = vF;
   sm.FRT[fidx] = rtF;
@@ -1018,7 +1027,7 @@ __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& s
   psi[1] = to_fixed(Fx, sc, &bad);
   psi[2] = to_fixed(Fy, sc, &bad);
   psi[3] = to_fixed(FE, sc, &bad);
-  if (bad) atomicOr(a.flag, 2);
+  raise_flag(a.flag, bad != 0, 2);
 }
 
 // Flux of two opposite faces into the cell frame (eq. fluxEq):
@@ -1072,6 +1081,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
   const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
   const int x0 = bx * G::TX, y0 = by * G::TY;
   const T kappa = T(a.kappa), apre = T(a.a_pre);
+  // a solve whose status flag is already raised has failed: its state is no
+  // longer used, so its tiles do no work (one read per workgroup, shared
+  // through LDS so that the whole workgroup takes the same branch)
+  if (tid == 0) sm.skip = *static_cast<volatile int*>(a.flag);
+  __syncthreads();
+  if (sm.skip) return;
 
   // ---- 0. halo tile: ghost resolution, frame, first QE half step, phi-bar-plus
 #pragma unroll 1
@@ -1219,11 +1234,11 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
 #pragma unroll
     for (int i = 0; i < QG; ++i) n2[QF + i] -= rg2 * wg<D, T>(i);
     qe_half<D, T>(n2, n2 + QF, kappa);
-    if (!(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0]))) atomicOr(a.flag, 1);
+    raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
     bool over = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) over |= (U2[q] > (1LL << 62)) || (U2[q] < -(1LL << 62));
-    if (over) atomicOr(a.flag, 2);
+    raise_flag(a.flag, over, 2);
     const size_t cell = size_t(x0 + cx) + size_t(a.nx) * size_t(D == 2 ? y0 + cy : 0);
     T* nout = static_cast<T*>(a.n_out);
 #pragma unroll

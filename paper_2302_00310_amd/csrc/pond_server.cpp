@@ -114,6 +114,13 @@ struct pond_server {
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   int n_tab = 0, total_tiles = 0, phase = 0;
   unsigned tf_mask = 0;  // transforms present in the resident set (bit per transform)
+  // counters for pond_server_stats (written by the server thread under mu)
+  double st_admit = 0.0, st_table = 0.0, st_capture = 0.0, st_retire = 0.0;
+  double st_cell_updates = 0.0, st_chunks = 0.0, st_changes = 0.0, st_captures = 0.0;
+  double st_gpu = 0.0;  // event-timed GPU seconds of the step chunks
+  // chunks in flight: (start, end) events; finished ones are timed and recycled
+  std::deque<std::pair<hipEvent_t, hipEvent_t>> inflight;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;
   int device = 0;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
@@ -132,6 +139,16 @@ int tiles_of(const pond_config& c) {
 
 // Rebuild the device table of resident solves.
 int upload_table(pond_server* S) {
+  const double t = S->now();
+  struct Acc {
+    pond_server* S;
+    double t;
+    ~Acc() {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->st_table += S->now() - t;
+      S->st_changes += 1.0;
+    }
+  } acc{S, t};
   drop_graphs(S);
   int tile = 0;
   for (size_t k = 0; k < S->active.size(); ++k) {
@@ -166,6 +183,7 @@ int run_steps(pond_server* S, int K) {
   auto key = std::make_pair(K, par0);
   auto it = S->graphs.find(key);
   if (it == S->graphs.end()) {
+    const double t = S->now();
     hipError_t err = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
     for (int j = 0; j < K; ++j)
@@ -179,10 +197,30 @@ int run_steps(pond_server* S, int K) {
     hipGraphDestroy(g);
     if (err != hipSuccess) return hip_fail(err, "hipGraphInstantiate");
     it = S->graphs.emplace(key, ex).first;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st_capture += S->now() - t;
+    S->st_captures += 1.0;
   }
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (!S->spare.empty()) {
+    ev = S->spare.back();
+    S->spare.pop_back();
+  } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+    return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
+  }
+  hipEventRecord(ev.first, S->stream);
   hipError_t err = hipGraphLaunch(it->second, S->stream);
   if (err != hipSuccess) return hip_fail(err, "hipGraphLaunch");
+  hipEventRecord(ev.second, S->stream);
+  S->inflight.push_back(ev);
   S->phase += K;
+  double cu = 0.0;
+  for (Job* j : S->active) cu += double(j->cfg.nx) * j->cfg.ny * K;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st_cell_updates += cu;
+    S->st_chunks += 1.0;
+  }
   for (Job* j : S->active) {
     j->remaining -= K;
     j->st->cur ^= (K & 1);
@@ -203,11 +241,29 @@ void finish(pond_server* S, Job* j, int status) {
   S->cv.notify_all();
 }
 
+// Time the chunks that have finished (all of them when wait is set).
+void harvest(pond_server* S, bool wait) {
+  while (!S->inflight.empty()) {
+    auto ev = S->inflight.front();
+    if (wait) hipEventSynchronize(ev.second);
+    else if (hipEventQuery(ev.second) != hipSuccess) break;
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, ev.first, ev.second);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->st_gpu += 1e-3 * ms;
+    }
+    S->inflight.pop_front();
+    S->spare.push_back(ev);
+  }
+}
+
 void serve(pond_server* S) {
   hipSetDevice(S->device);
   std::vector<Job*> admit;
   bool changed = false;
   for (;;) {
+    harvest(S, false);
     {
       std::unique_lock<std::mutex> lk(S->mu);
       while (!S->stop && !S->queue.empty() &&
@@ -226,6 +282,7 @@ void serve(pond_server* S) {
       }
     }
     // admission: state in the job's arena region, comoving equilibrium on device
+    const double t_adm = S->now();
     for (Job* j : admit) {
       pond_state* st = nullptr;
       int rc = pond_create(&j->cfg, S->arena + j->off, j->bytes, S->stream, &st);
@@ -253,6 +310,10 @@ void serve(pond_server* S) {
       S->active.push_back(j);
       changed = true;
     }
+    if (!admit.empty()) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->st_admit += S->now() - t_adm;
+    }
     admit.clear();
     if (S->active.empty()) continue;
     if (changed) {
@@ -263,6 +324,7 @@ void serve(pond_server* S) {
       }
       changed = false;
     }
+    harvest(S, false);
     int K = kChunk;
     for (Job* j : S->active) K = std::min(K, j->remaining);
     if (run_steps(S, K) != POND_OK) {
@@ -276,6 +338,7 @@ void serve(pond_server* S) {
     for (Job* j : S->active) any |= j->remaining == 0;
     if (!any) continue;
     std::vector<Job*> keep;
+    const double t_ret = S->now();
     for (Job* j : S->active) {
       if (j->remaining > 0) {
         keep.push_back(j);
@@ -289,6 +352,8 @@ void serve(pond_server* S) {
     }
     S->active.swap(keep);
     changed = true;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st_retire += S->now() - t_ret;
   }
 }
 
@@ -388,6 +453,21 @@ int pond_poll(pond_server* S, uint64_t id, pond_result* res) {
   return status;
 }
 
+int pond_server_stats(pond_server* S, double out[9]) {
+  if (!S || !out) return fail(POND_ERR_INVALID, "null server or output");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out[0] = S->now();
+  out[1] = S->st_cell_updates;
+  out[2] = S->st_chunks;
+  out[3] = S->st_changes;
+  out[4] = S->st_admit;
+  out[5] = S->st_retire;
+  out[6] = S->st_table;
+  out[7] = S->st_capture;
+  out[8] = S->st_gpu;
+  return POND_OK;
+}
+
 int pond_server_destroy(pond_server* S) {
   if (!S) return POND_OK;
   {
@@ -402,6 +482,11 @@ int pond_server_destroy(pond_server* S) {
     S->cv.notify_all();
   }
   if (S->th.joinable()) S->th.join();
+  harvest(S, true);
+  for (auto& ev : S->spare) {
+    hipEventDestroy(ev.first);
+    hipEventDestroy(ev.second);
+  }
   drop_graphs(S);
   if (S->host_tab) hipHostFree(S->host_tab);
   hipStreamSynchronize(S->stream);

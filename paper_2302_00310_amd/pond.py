@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "pond_server_create": ([vp, sz, vp, i, C.POINTER(vp)], i),
         "pond_submit": ([vp, C.POINTER(pond_request), C.POINTER(C.c_uint64)], i),
         "pond_poll": ([vp, C.c_uint64, C.POINTER(pond_result)], i),
+        "pond_server_stats": ([vp, C.POINTER(C.c_double)], i),
         "pond_server_destroy": ([vp], i),
     }
     for name, (args, res) in sig.items():
@@ -101,7 +102,8 @@ def exported_symbols():
     return ["pond_last_error", "pond_state_bytes", "pond_create", "pond_init_fields", "pond_step",
             "pond_moments", "pond_totals", "pond_totals_fixed", "pond_export_state",
             "pond_get_time", "pond_save", "pond_load", "pond_destroy", "pond_lattice_constants",
-            "pond_server_create", "pond_submit", "pond_poll", "pond_server_destroy"]
+            "pond_server_create", "pond_submit", "pond_poll", "pond_server_stats",
+            "pond_server_destroy"]
 
 
 def last_error() -> str:
@@ -302,6 +304,14 @@ def pond_poll(srv, rid: int, n: int):
         raise PondError(rc, last_error())
     times = {"t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done, "tag": res.tag}
     return rc, out, times
+
+
+def pond_server_stats(srv) -> dict:
+    out = (C.c_double * 9)()
+    check(load_library().pond_server_stats(srv, out))
+    keys = ("elapsed_s", "cell_updates", "chunks", "set_changes", "admit_s", "retire_s",
+            "table_s", "capture_s", "gpu_s")
+    return dict(zip(keys, list(out)))
 
 
 def pond_server_destroy(srv):
