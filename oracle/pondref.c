@@ -254,6 +254,85 @@ int pondref_transform_matrix_full(int dim, int lattice, const double src[3],
   return rc ? fail("singular moment system") : 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Multiscale frame transformation (Sec. III C, eqs. lifting1, projection1). */
+/*                                                                          */
+/* Between a source lattice with q1s nodes per axis and a target with q1t,  */
+/* both Hermite-Grad expansions (eq. GradsProjection):                       */
+/*  - same lattice: Grad's projection of order q1 - 1 (the map above);      */
+/*  - lifting (D2Q9 -> D2Q16): the moments the D2Q9 populations carry       */
+/*    (Hermite moments of total order <= 2) are kept and the missing         */
+/*    third-order ones take their equilibrium value.  reading: equilibrium  */
+/*    in the source's comoving frame, where the Maxwellian's third Hermite  */
+/*    moments vanish (a Galilean-invariant choice); the lifted D2Q16 set is */
+/*    built there and then mapped to the target frame by Grad's projection; */
+/*  - projection (D2Q16 -> D2Q9): Grad's expansion of order 2 in the target */
+/*    frame from the Hermite moments of the D2Q16 populations.               */
+/* ------------------------------------------------------------------------ */
+static int ms_matrix(int transform, int q1s, const double src[3], int q1t, const double dst[3],
+                     double* G) {
+  lat1 Ls, Lt;
+  lattice_get(q1s == 4 ? 0 : 1, &Ls);
+  lattice_get(q1t == 4 ? 0 : 1, &Lt);
+  if (q1s == q1t) return transform_matrix(2, &Ls, transform, src, dst, G);
+  if (q1s == 3) {
+    /* lifting: own-frame D2Q16 expansion with alpha_ab (a + b <= 2) from the
+       D2Q9 populations and alpha_ab = 0 for a + b = 3 */
+    double lift[16 * 9], Gt[256];
+    for (int ky = 0; ky < 4; ky++)
+      for (int kx = 0; kx < 4; kx++)
+        for (int my = 0; my < 3; my++)
+          for (int mx = 0; mx < 3; mx++) {
+            double acc = 0.0;
+            for (int a = 0; a <= 2; a++)
+              for (int b = 0; a + b <= 2; b++)
+                acc += hermite(a, Lt.c[kx]) * hermite(b, Lt.c[ky]) * hermite(a, Ls.c[mx]) *
+                       hermite(b, Ls.c[my]) / (factorial[a] * factorial[b]);
+            lift[(kx + 4 * ky) * 9 + (mx + 3 * my)] = Lt.w[kx] * Lt.w[ky] * acc;
+          }
+    if (transform_matrix(2, &Lt, PONDREF_TF_GRAD, src, dst, Gt)) return -1;
+    for (int k = 0; k < 16; k++)
+      for (int m = 0; m < 9; m++) {
+        double acc = 0.0;
+        for (int j = 0; j < 16; j++) acc += Gt[k * 16 + j] * lift[j * 9 + m];
+        G[k * 9 + m] = acc;
+      }
+    return 0;
+  }
+  /* projection */
+  double sc, dx, dy;
+  frame_shift(src, dst, &sc, &dx, &dy);
+  for (int ky = 0; ky < 3; ky++)
+    for (int kx = 0; kx < 3; kx++)
+      for (int my = 0; my < 4; my++)
+        for (int mx = 0; mx < 4; mx++) {
+          const double xm = sc * Ls.c[mx] + dx, ym = sc * Ls.c[my] + dy;
+          double acc = 0.0;
+          for (int a = 0; a <= 2; a++)
+            for (int b = 0; a + b <= 2; b++)
+              acc += hermite(a, Lt.c[kx]) * hermite(b, Lt.c[ky]) * hermite(a, xm) *
+                     hermite(b, ym) / (factorial[a] * factorial[b]);
+          G[(kx + 3 * ky) * 16 + (mx + 4 * my)] = Lt.w[kx] * Lt.w[ky] * acc;
+        }
+  return 0;
+}
+
+int pondref_ms_matrix(int q1s, const double src[3], int q1t, const double dst[3], double* G) {
+  if ((q1s != 3 && q1s != 4) || (q1t != 3 && q1t != 4)) return fail("q1 must be 3 or 4");
+  if (src[2] <= 0.0 || dst[2] <= 0.0) return fail("frame temperature must be positive");
+  if (ms_matrix(PONDREF_TF_GRAD, q1s, src, q1t, dst, G)) return fail("singular moment system");
+  return 0;
+}
+
+/* rectangular: out (Qt) = G (Qt x Qs) in (Qs) */
+static void matvec_r(int Qt, int Qs, const double* G, const double* in, double* out) {
+  for (int k = 0; k < Qt; k++) {
+    double acc = 0.0;
+    for (int m = 0; m < Qs; m++) acc += G[k * Qs + m] * in[m];
+    out[k] = acc;
+  }
+}
+
 static void matvec(int Q, const double* G, const double* in, double* out) {
   for (int k = 0; k < Q; k++) {
     double acc = 0.0;
@@ -284,6 +363,15 @@ struct pondref_state {
   double* gbp;       /* [cell][Qg] */
   double* ffx; double* gfx; double* lfx; /* x-faces */
   double* ffy; double* gfy; double* lfy; /* y-faces */
+  /* f-lattice per cell, as the 1D node count q1 (4: D2Q16 / D1Q4, 3: D2Q9),
+     and per face; the multiscale switch indicator of the last step */
+  unsigned char* lat;
+  unsigned char* latfx; unsigned char* latfy;
+  unsigned char* flag;
+  double* theta;
+  /* per-lattice tables, index 0: q1 = 4, index 1: q1 = 3 (2D tensor or 1D) */
+  int Qq[2];
+  double Wq[2][QMAX], cxq[2][QMAX], cyq[2][QMAX];
   double dt, dx, tau1, tau2, cv;
   int dt_fixed;
   long nstep;
@@ -322,6 +410,12 @@ static int check_config(const pondref_config* c) {
   if (c->limiter != PONDREF_LIM_VANLEER && c->limiter != PONDREF_LIM_MINMOD)
     return fail("unknown limiter");
   if (c->n_corr < 0) return fail("n_corr must be >= 0");
+  if (c->flat < 0 || c->flat > 2) return fail("unknown f-lattice");
+  if (c->flat != PONDREF_F_D2Q16 && c->dim != 2) return fail("the D2Q9 and multiscale f-lattices are 2D");
+  if (c->flat == PONDREF_F_MULTISCALE && c->transform != PONDREF_TF_GRAD)
+    return fail("the multiscale deployment uses Grad's projection");
+  if (c->flat == PONDREF_F_MULTISCALE && !(c->ms_threshold >= 0.0))
+    return fail("the multiscale threshold must be >= 0");
   const int nside = c->dim == 2 ? 4 : 2;
   for (int k = 0; k < nside; k++)
     if (c->bc[k] < 0 || c->bc[k] > 2) return fail("unknown boundary condition");
@@ -364,9 +458,19 @@ int pondref_create(const pondref_config* cfg, pondref_state** out) {
         s->cgy[i] = s->Lg.c[iy];
       }
   }
+  /* per-lattice tables: D2Q16 / D1Q4 (index 0) and the D2Q9 f-lattice
+     (index 1, tensor D1Q3, i = i_x + 3 i_y) */
+  s->Qq[0] = s->Qf;
+  for (int i = 0; i < s->Qf; i++) { s->Wq[0][i] = s->Wf[i]; s->cxq[0][i] = s->cfx[i]; s->cyq[0][i] = s->cfy[i]; }
+  s->Qq[1] = s->Qg;
+  for (int i = 0; i < s->Qg; i++) { s->Wq[1][i] = s->Wg[i]; s->cxq[1][i] = s->cgx[i]; s->cyq[1][i] = s->cgy[i]; }
   s->nxp = cfg->nx + 2 * NG;
   s->nyp = s->D == 2 ? cfg->ny + 2 * NG : 1;
   const size_t nc = (size_t)s->nxp * s->nyp;
+  s->lat = (unsigned char*)malloc(nc);
+  s->flag = (unsigned char*)calloc(nc, 1);
+  memset(s->lat, cfg->flat == PONDREF_F_D2Q9 ? 3 : 4, nc);
+  s->theta = (double*)calloc((size_t)cfg->nx * cfg->ny, sizeof(double));
   s->f = (double*)calloc(nc * s->Qf, sizeof(double));
   s->g = (double*)calloc(nc * s->Qg, sizeof(double));
   s->fr = (double*)calloc(nc * 3, sizeof(double));
@@ -377,6 +481,8 @@ int pondref_create(const pondref_config* cfg, pondref_state** out) {
   s->ffx = (double*)calloc(nfx * s->Qf, sizeof(double));
   s->gfx = (double*)calloc(nfx * s->Qg, sizeof(double));
   s->lfx = (double*)calloc(nfx * 3, sizeof(double));
+  s->latfx = (unsigned char*)calloc(nfx, 1);
+  s->latfy = (unsigned char*)calloc(nfy ? nfy : 1, 1);
   if (nfy) {
     s->ffy = (double*)calloc(nfy * s->Qf, sizeof(double));
     s->gfy = (double*)calloc(nfy * s->Qg, sizeof(double));
@@ -393,6 +499,7 @@ void pondref_destroy(pondref_state* s) {
   free(s->f); free(s->g); free(s->fr); free(s->fbp); free(s->gbp);
   free(s->ffx); free(s->gfx); free(s->lfx);
   free(s->ffy); free(s->gfy); free(s->lfy);
+  free(s->lat); free(s->latfx); free(s->latfy); free(s->flag); free(s->theta);
   free(s);
 }
 
@@ -402,21 +509,25 @@ void pondref_destroy(pondref_state* s) {
 
 /* Comoving equilibria: f^eq = rho W_i (eq. feqPond), g^eq = (C_v - D/2) T rho W_i
    (eq. geqPond), written in the comoving frame lambda = {u, T}. */
-static void comoving_eq(const pondref_state* s, double rho, double T, double* feq, double* geq) {
-  for (int i = 0; i < s->Qf; i++) feq[i] = rho * s->Wf[i];
+static void comoving_eq(const pondref_state* s, int q1, double rho, double T, double* feq,
+                        double* geq) {
+  const int l = q1 == 4 ? 0 : 1;
+  for (int i = 0; i < s->Qq[l]; i++) feq[i] = rho * s->Wq[l][i];
   const double e = (s->cv - 0.5 * s->D) * T * rho;
   for (int i = 0; i < s->Qg; i++) geq[i] = e * s->Wg[i];
 }
 
 /* Conservation laws (eq. ConservationLaws and eq. E): density, velocity and
    temperature from f and g written in frame fr, v_i = sqrt(T) c_i + u. */
-static void moments(const pondref_state* s, const double* f, const double* g, const double fr[3],
-                    double* rho, double* ux, double* uy, double* T, double* rhoE) {
+static void moments(const pondref_state* s, int q1, const double* f, const double* g,
+                    const double fr[3], double* rho, double* ux, double* uy, double* T,
+                    double* rhoE) {
+  const int l = q1 == 4 ? 0 : 1;
   const double rt = sqrt(fr[2]);
   double m0 = 0.0, mx = 0.0, my = 0.0, e = 0.0;
-  for (int i = 0; i < s->Qf; i++) {
-    const double vx = rt * s->cfx[i] + fr[0];
-    const double vy = s->D == 2 ? rt * s->cfy[i] + fr[1] : 0.0;
+  for (int i = 0; i < s->Qq[l]; i++) {
+    const double vx = rt * s->cxq[l][i] + fr[0];
+    const double vy = s->D == 2 ? rt * s->cyq[l][i] + fr[1] : 0.0;
     m0 += f[i];
     mx += vx * f[i];
     my += vy * f[i];
@@ -438,7 +549,8 @@ static double cfl_dt(const pondref_config* c, const double* rho, const double* u
                      const double* uy, const double* p) {
   /* CFL = max|v_ia| dt / dx = 0.2 (Sec. V); the max runs over cells,
      populations and axes of |sqrt(T) c_ia + u_a|, at t = 0 (reading). */
-  const double cmax = sqrt(3.0 + sqrt(6.0));
+  /* the largest node of the f-lattice in use (D2Q9 alone: sqrt 3) */
+  const double cmax = (c->dim == 2 && c->flat == PONDREF_F_D2Q9) ? sqrt(3.0) : sqrt(3.0 + sqrt(6.0));
   const double dx = c->dx > 0.0 ? c->dx : 1.0 / c->nx;
   double vmax = 0.0;
   const size_t n = (size_t)c->nx * c->ny;
@@ -476,7 +588,7 @@ int pondref_init_fields(pondref_state* s, const double* rho, const double* ux, c
       fr[0] = ux[k];
       fr[1] = s->D == 2 ? uy[k] : 0.0;
       fr[2] = p[k] / rho[k];
-      comoving_eq(s, rho[k], fr[2], s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg);
+      comoving_eq(s, s->lat[c], rho[k], fr[2], s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg);
     }
   if (!s->dt_fixed) s->dt = cfl_dt(&s->cfg, rho, ux, uy, p);
   set_times(s);
@@ -529,16 +641,79 @@ static void fill_ghosts(pondref_state* s) {
       const int c = cidx(s, x, y);
       double* fr = s->fr + 3 * c;
       if (side >= 0) {
+        /* reading: an inflow ghost takes the f-lattice of the interior cell
+           next to it */
+        const int bx = sx, by = s->D == 2 ? (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) : 0;
+        s->lat[c] = s->lat[cidx(s, bx, by)];
         const double* st = s->cfg.inflow[side];
         fr[0] = st[1];
         fr[1] = s->D == 2 ? st[2] : 0.0;
         fr[2] = st[3] / st[0];
-        comoving_eq(s, st[0], fr[2], s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg);
+        comoving_eq(s, s->lat[c], st[0], fr[2], s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg);
       } else {
         const int src = cidx(s, sx, sy);
+        s->lat[c] = s->lat[src];
         memcpy(fr, s->fr + 3 * src, 3 * sizeof(double));
         memcpy(s->f + (size_t)c * s->Qf, s->f + (size_t)src * s->Qf, s->Qf * sizeof(double));
         memcpy(s->g + (size_t)c * s->Qg, s->g + (size_t)src * s->Qg, s->Qg * sizeof(double));
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multiscale switch (Sec. IV C, Sec. V multiscale framework): D2Q16 where   */
+/* the flow velocity and temperature gradients are steep, D2Q9 elsewhere.    */
+/* reading (threshold and stencil are not given): central differences of    */
+/* the cell frames, indicator theta = dx (|grad u| / sqrt(gamma T) +          */
+/* |grad T| / T) with Frobenius / Euclidean norms, D2Q16 within two cells    */
+/* (Chebyshev distance) of a cell with theta >= ms_threshold.  Ghost flags   */
+/* follow the ghost rule of the populations (inflow: the next interior      */
+/* cell).  Cells whose lattice changes have their populations lifted or     */
+/* projected in their own frame.  Needs the ghost frames filled.            */
+/* ------------------------------------------------------------------------ */
+static void switch_lattices(pondref_state* s) {
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  const double thr = s->cfg.ms_threshold, gam = s->cfg.gamma;
+  for (int y = 0; y < ny; y++)
+    for (int x = 0; x < nx; x++) {
+      const double* xp = s->fr + 3 * cidx(s, x + 1, y);
+      const double* xm = s->fr + 3 * cidx(s, x - 1, y);
+      const double* yp = s->fr + 3 * cidx(s, x, y + 1);
+      const double* ym = s->fr + 3 * cidx(s, x, y - 1);
+      const double T = s->fr[3 * cidx(s, x, y) + 2];
+      const double uxx = 0.5 * (xp[0] - xm[0]), uyx = 0.5 * (xp[1] - xm[1]);
+      const double uxy = 0.5 * (yp[0] - ym[0]), uyy = 0.5 * (yp[1] - ym[1]);
+      const double Tx = 0.5 * (xp[2] - xm[2]), Ty = 0.5 * (yp[2] - ym[2]);
+      const double gu = sqrt(uxx * uxx + uyx * uyx + uxy * uxy + uyy * uyy);
+      const double gT = sqrt(Tx * Tx + Ty * Ty);
+      const double th = gu / sqrt(gam * T) + gT / T;
+      s->theta[x + nx * y] = th;
+      s->flag[cidx(s, x, y)] = th >= thr;
+    }
+  for (int y = -NG; y < ny + NG; y++)
+    for (int x = -NG; x < nx + NG; x++) {
+      if (x >= 0 && x < nx && y >= 0 && y < ny) continue;
+      int side = -1;
+      const int sx = resolve_axis(x, nx, s->cfg.bc[0], s->cfg.bc[1], &side, 0);
+      int sy = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+      if (side < 0) sy = resolve_axis(y, ny, s->cfg.bc[2], s->cfg.bc[3], &side, 2);
+      s->flag[cidx(s, x, y)] = s->flag[cidx(s, sx, sy)];
+    }
+  for (int y = 0; y < ny; y++)
+    for (int x = 0; x < nx; x++) {
+      int hi = 0;
+      for (int j = -2; j <= 2; j++)
+        for (int i = -2; i <= 2; i++) hi |= s->flag[cidx(s, x + i, y + j)];
+      const int c = cidx(s, x, y);
+      const int q1 = hi ? 4 : 3;
+      if (q1 != s->lat[c]) {
+        const int qo = s->lat[c];
+        double G[256], tmp[QMAX];
+        double* f = s->f + (size_t)c * s->Qf;
+        ms_matrix(PONDREF_TF_GRAD, qo, s->fr + 3 * c, q1, s->fr + 3 * c, G);
+        matvec_r(q1 * q1, qo * qo, G, f, tmp);
+        for (int i = 0; i < s->Qf; i++) f[i] = i < q1 * q1 ? tmp[i] : 0.0;
+        s->lat[c] = (unsigned char)q1;
       }
     }
 }
@@ -552,9 +727,17 @@ static void fill_ghosts(pondref_state* s) {
 /* the stored f~ (reading: the QE term is linear in the third Hermite        */
 /* moment, which the variable transform only rescales).                      */
 /* ------------------------------------------------------------------------ */
-static void qe_half_step(const pondref_state* s, double* f, double* g) {
+static void qe_half_step(const pondref_state* s, int q1, double* f, double* g) {
   const double kappa = 0.5 * s->dt * (1.0 / s->tau1 - 1.0 / s->tau2);
   if (kappa == 0.0) return;
+  if (s->D == 2 && q1 == 3) {
+    /* reading: the D2Q9 f-lattice carries no third-order moments, so only
+       the g part of the quasi-equilibrium relaxation acts on it */
+    double agx = 0.0, agy = 0.0;
+    for (int i = 0; i < 9; i++) { agx += g[i] * s->cgx[i]; agy += g[i] * s->cgy[i]; }
+    for (int i = 0; i < 9; i++) g[i] += kappa * s->Wg[i] * (agx * s->cgx[i] + agy * s->cgy[i]);
+    return;
+  }
   if (s->D == 1) {
     double a3 = 0.0, ag = 0.0;
     for (int i = 0; i < 4; i++) a3 += f[i] * hermite(3, s->cfx[i]);
@@ -597,6 +780,20 @@ static double limiter(int kind, double a, double b) {
   return (a * fabs(b) + fabs(a) * b) / den;
 }
 
+/* f populations from lattice q1s in frame src to lattice q1t in frame dst
+   (1D: the D1Q4 map of the configured transform). */
+static void xf_f(const pondref_state* s, int q1s, const double src[3], int q1t,
+                 const double dst[3], const double* in, double* out) {
+  double G[256];
+  if (s->D == 1) {
+    transform_matrix(1, &s->Lf, s->cfg.transform, src, dst, G);
+    matvec(4, G, in, out);
+    return;
+  }
+  ms_matrix(s->cfg.transform, q1s, src, q1t, dst, G);
+  matvec_r(q1t * q1t, q1s * q1s, G, in, out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Flux evaluation at one face (Sec. IV A 2).                                */
 /* ------------------------------------------------------------------------ */
@@ -617,14 +814,22 @@ static double reconstruct(int lim, double PU, double Pm, double Pp, double Ptm, 
 }
 
 static void face_flux(const pondref_state* s, const face_stencil* st, double* fout, double* gout,
-                      double* lout) {
+                      double* lout, unsigned char* qout) {
   const int D = s->D, Qf = s->Qf, Qg = s->Qg;
+  /* reading: a face uses the higher-order f-lattice of its two cells, so
+     D2Q16 regions extend to their boundary faces (the stencil's other
+     cells are lifted or projected into it) */
+  const int qF = s->lat[st->L] > s->lat[st->R] ? s->lat[st->L] : s->lat[st->R];
+  const int lq = qF == 4 ? 0 : 1;
+  const int QF = s->Qq[lq];
+  const double* fcx = s->cxq[lq];
+  const double* fcy = s->cyq[lq];
   const int twod = D == 2;
   const double lam = s->dt / s->dx;
   const int ncell = twod ? 8 : 4;
   const int cells[8] = {st->L, st->R, st->LL, st->RR, st->Lp, st->Lm, st->Rp, st->Rm};
   double Pf[8][QMAX], Pg[8][QMAX];
-  double Gf[QMAX * QMAX], Gg[81];
+  double Gg[81];
   double fbar[QMAX], gbar[9];
   const double* frL = s->fr + 3 * st->L;
   const double* frR = s->fr + 3 * st->R;
@@ -637,17 +842,16 @@ static void face_flux(const pondref_state* s, const face_stencil* st, double* fo
     /* transform the stencil's phi-bar-plus into the face frame */
     for (int k = 0; k < ncell; k++) {
       const int c = cells[k];
-      transform_matrix(D, &s->Lf, s->cfg.transform, s->fr + 3 * c, lF, Gf);
-      matvec(Qf, Gf, s->fbp + (size_t)c * Qf, Pf[k]);
+      xf_f(s, s->lat[c], s->fr + 3 * c, qF, lF, s->fbp + (size_t)c * Qf, Pf[k]);
       transform_matrix(D, &s->Lg, s->cfg.transform, s->fr + 3 * c, lF, Gg);
       matvec(Qg, Gg, s->gbp + (size_t)c * Qg, Pg[k]);
     }
     /* eq. InterfacePop with MUSCL at the departure point */
     const double rt = sqrt(lF[2]);
     for (int pop = 0; pop < 2; pop++) {
-      const int Q = pop == 0 ? Qf : Qg;
-      const double* cx = pop == 0 ? s->cfx : s->cgx;
-      const double* cy = pop == 0 ? s->cfy : s->cgy;
+      const int Q = pop == 0 ? QF : Qg;
+      const double* cx = pop == 0 ? fcx : s->cgx;
+      const double* cy = pop == 0 ? fcy : s->cgy;
       double (*P)[QMAX] = pop == 0 ? Pf : Pg;
       double* out = pop == 0 ? fbar : gbar;
       for (int i = 0; i < Q; i++) {
@@ -671,9 +875,9 @@ static void face_flux(const pondref_state* s, const face_stencil* st, double* fo
     }
     /* macroscopic fields at the face from f-bar and g-bar in lambda_F */
     double m0 = 0.0, m1[2] = {0.0, 0.0}, e = 0.0;
-    for (int i = 0; i < Qf; i++) {
-      const double vx = rt * s->cfx[i] + lF[0];
-      const double vy = twod ? rt * s->cfy[i] + lF[1] : 0.0;
+    for (int i = 0; i < QF; i++) {
+      const double vx = rt * fcx[i] + lF[0];
+      const double vy = twod ? rt * fcy[i] + lF[1] : 0.0;
       m0 += fbar[i];
       m1[0] += vx * fbar[i];
       m1[1] += vy * fbar[i];
@@ -696,14 +900,15 @@ static void face_flux(const pondref_state* s, const face_stencil* st, double* fo
      (eq. NonComovingEq) */
   const double lb[3] = {u_b[0], u_b[1], T_b};
   double feqc[QMAX], geqc[9], feq[QMAX], geq[9];
-  comoving_eq(s, rho_b, T_b, feqc, geqc);
-  transform_matrix(D, &s->Lf, s->cfg.transform, lb, lF, Gf);
-  matvec(Qf, Gf, feqc, feq);
+  comoving_eq(s, qF, rho_b, T_b, feqc, geqc);
+  xf_f(s, qF, lb, qF, lF, feqc, feq);
   transform_matrix(D, &s->Lg, s->cfg.transform, lb, lF, Gg);
   matvec(Qg, Gg, geqc, geq);
   /* invert eq. FluxTransf: phi-bar = phi - (dt/4) Omega with BGK Omega */
   const double tau = s->tau1, dt = s->dt;
-  for (int i = 0; i < Qf; i++) fout[i] = (4.0 * tau * fbar[i] + dt * feq[i]) / (4.0 * tau + dt);
+  for (int i = 0; i < Qf; i++)
+    fout[i] = i < QF ? (4.0 * tau * fbar[i] + dt * feq[i]) / (4.0 * tau + dt) : 0.0;
+  *qout = (unsigned char)qF;
   for (int i = 0; i < Qg; i++) gout[i] = (4.0 * tau * gbar[i] + dt * geq[i]) / (4.0 * tau + dt);
   lout[0] = lF[0];
   lout[1] = lF[1];
@@ -718,12 +923,18 @@ static void one_step(pondref_state* s) {
   const int twod = D == 2;
   const double tau = s->tau1, dt = s->dt, lam = dt / s->dx;
 
+  /* multiscale: choose each cell's f-lattice for this step (Sec. IV C) */
+  if (twod && s->cfg.flat == PONDREF_F_MULTISCALE) {
+    fill_ghosts(s);
+    switch_lattices(s);
+  }
+
   /* Strang splitting, first quasi-equilibrium half step (Sec. IV B) */
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++) {
       const int c = cidx(s, x, y);
-      qe_half_step(s, s->f + (size_t)c * Qf, s->g + (size_t)c * Qg);
+      qe_half_step(s, s->lat[c], s->f + (size_t)c * Qf, s->g + (size_t)c * Qg);
     }
 
   fill_ghosts(s);
@@ -738,10 +949,11 @@ static void one_step(pondref_state* s) {
       const int c = cidx(s, x, y);
       const double* f = s->f + (size_t)c * Qf;
       const double* g = s->g + (size_t)c * Qg;
+      const int Qc = s->Qq[s->lat[c] == 4 ? 0 : 1];
       double rho = 0.0;
-      for (int i = 0; i < Qf; i++) rho += f[i];
-      double feq[QMAX], geq[9];
-      comoving_eq(s, rho, s->fr[3 * c + 2], feq, geq);
+      for (int i = 0; i < Qc; i++) rho += f[i];
+      double feq[QMAX] = {0}, geq[9];
+      comoving_eq(s, s->lat[c], rho, s->fr[3 * c + 2], feq, geq);
       for (int i = 0; i < Qf; i++)
         s->fbp[(size_t)c * Qf + i] = ((2.0 * tau - 0.5 * dt) * f[i] + 1.5 * dt * feq[i]) / (2.0 * tau + dt);
       for (int i = 0; i < Qg; i++)
@@ -763,7 +975,7 @@ static void one_step(pondref_state* s) {
         st.Lp = st.Lm = st.Rp = st.Rm = 0;
       }
       const size_t fi = (size_t)i + (size_t)(nx + 1) * y;
-      face_flux(s, &st, s->ffx + fi * Qf, s->gfx + fi * Qg, s->lfx + fi * 3);
+      face_flux(s, &st, s->ffx + fi * Qf, s->gfx + fi * Qg, s->lfx + fi * 3, s->latfx + fi);
     }
   if (twod) {
 #pragma omp parallel for schedule(static)
@@ -776,7 +988,7 @@ static void one_step(pondref_state* s) {
         st.Lp = cidx(s, x + 1, j - 1); st.Lm = cidx(s, x - 1, j - 1);
         st.Rp = cidx(s, x + 1, j); st.Rm = cidx(s, x - 1, j);
         const size_t fi = (size_t)x + (size_t)nx * j;
-        face_flux(s, &st, s->ffy + fi * Qf, s->gfy + fi * Qg, s->lfy + fi * 3);
+        face_flux(s, &st, s->ffy + fi * Qf, s->gfy + fi * Qg, s->lfy + fi * 3, s->latfy + fi);
       }
   }
 
@@ -790,33 +1002,36 @@ static void one_step(pondref_state* s) {
       double* f = s->f + (size_t)c * Qf;
       double* g = s->g + (size_t)c * Qg;
       double* fr = s->fr + 3 * c;
-      double Gf[QMAX * QMAX], Gg[81];
-      double flf[QMAX] = {0}, flg[9] = {0}, tf[QMAX], tg[9];
+      double Gg[81];
+      double flf[QMAX] = {0}, flg[9] = {0}, tf[QMAX] = {0}, tg[9];
       const double rt = sqrt(fr[2]);
+      const int qc = s->lat[c], lc = qc == 4 ? 0 : 1, Qc = s->Qq[lc];
       const int nface = twod ? 4 : 2;
       for (int k = 0; k < nface; k++) {
         /* faces: west (-x), east (+x), south (-y), north (+y) */
         const double* pf; const double* pg; const double* lf;
         double sign;
-        int axis;
+        int axis, qf;
         if (k < 2) {
           const size_t fi = (size_t)(x + k) + (size_t)(nx + 1) * y;
           pf = s->ffx + fi * Qf; pg = s->gfx + fi * Qg; lf = s->lfx + fi * 3;
+          qf = s->latfx[fi];
           sign = k == 0 ? -1.0 : 1.0;
           axis = 0;
         } else {
           const size_t fi = (size_t)x + (size_t)nx * (y + (k - 2));
           pf = s->ffy + fi * Qf; pg = s->gfy + fi * Qg; lf = s->lfy + fi * 3;
+          qf = s->latfy[fi];
           sign = k == 2 ? -1.0 : 1.0;
           axis = 1;
         }
-        transform_matrix(D, &s->Lf, s->cfg.transform, lf, fr, Gf);
-        matvec(Qf, Gf, pf, tf);
+        /* face populations into the cell's frame and f-lattice */
+        xf_f(s, qf, lf, qc, fr, pf, tf);
         transform_matrix(D, &s->Lg, s->cfg.transform, lf, fr, Gg);
         matvec(Qg, Gg, pg, tg);
         /* (v_i^lambda . n_c) in the cell frame */
-        for (int i = 0; i < Qf; i++) {
-          const double vn = axis == 0 ? rt * s->cfx[i] + fr[0] : rt * s->cfy[i] + fr[1];
+        for (int i = 0; i < Qc; i++) {
+          const double vn = axis == 0 ? rt * s->cxq[lc][i] + fr[0] : rt * s->cyq[lc][i] + fr[1];
           flf[i] += sign * vn * tf[i];
         }
         for (int i = 0; i < Qg; i++) {
@@ -825,25 +1040,24 @@ static void one_step(pondref_state* s) {
         }
       }
       double rho = 0.0;
-      for (int i = 0; i < Qf; i++) rho += f[i];
+      for (int i = 0; i < Qc; i++) rho += f[i];
       double feq[QMAX], geq[9];
-      comoving_eq(s, rho, fr[2], feq, geq);
-      for (int i = 0; i < Qf; i++) f[i] = b * f[i] + c_eq * feq[i] - lam * flf[i];
+      comoving_eq(s, qc, rho, fr[2], feq, geq);
+      for (int i = 0; i < Qc; i++) f[i] = b * f[i] + c_eq * feq[i] - lam * flf[i];
       for (int i = 0; i < Qg; i++) g[i] = b * g[i] + c_eq * geq[i] - lam * flg[i];
       /* reading: the step ends in the comoving frame of the updated
          moments (the frame of t_{n+1}, Sec. IV A 1) */
       double r2, ux, uy, T;
-      moments(s, f, g, fr, &r2, &ux, &uy, &T, NULL);
+      moments(s, qc, f, g, fr, &r2, &ux, &uy, &T, NULL);
       const double nfr[3] = {ux, twod ? uy : 0.0, T};
-      transform_matrix(D, &s->Lf, s->cfg.transform, fr, nfr, Gf);
-      matvec(Qf, Gf, f, tf);
+      xf_f(s, qc, fr, qc, nfr, f, tf);
       transform_matrix(D, &s->Lg, s->cfg.transform, fr, nfr, Gg);
       matvec(Qg, Gg, g, tg);
-      memcpy(f, tf, sizeof(double) * Qf);
+      memcpy(f, tf, sizeof(double) * Qc);
       memcpy(g, tg, sizeof(double) * Qg);
       memcpy(fr, nfr, sizeof nfr);
       /* second quasi-equilibrium half step */
-      qe_half_step(s, f, g);
+      qe_half_step(s, qc, f, g);
     }
   s->nstep++;
 }
@@ -859,7 +1073,7 @@ int pondref_qe_half_step(int dim, double kappa, double* f, double* g) {
   s->dt = 1.0;
   s->tau1 = 1.0;
   s->tau2 = 1.0 / (1.0 - 2.0 * kappa); /* so that (dt/2)(1/tau1 - 1/tau2) = kappa */
-  qe_half_step(s, f, g);
+  qe_half_step(s, 4, f, g);
   pondref_destroy(s);
   return 0;
 }
@@ -879,7 +1093,7 @@ int pondref_moments(const pondref_state* s, double* rho, double* ux, double* uy,
     for (int x = 0; x < nx; x++) {
       const int c = cidx(s, x, y), k = x + nx * y;
       double r, a, b, t;
-      moments(s, s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg, s->fr + 3 * c, &r, &a, &b, &t, NULL);
+      moments(s, s->lat[c], s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg, s->fr + 3 * c, &r, &a, &b, &t, NULL);
       if (rho) rho[k] = r;
       if (ux) ux[k] = a;
       if (uy) uy[k] = b;
@@ -895,7 +1109,7 @@ int pondref_totals(const pondref_state* s, double out[4]) {
     for (int x = 0; x < nx; x++) {
       const int c = cidx(s, x, y);
       double r, a, b, t, e;
-      moments(s, s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg, s->fr + 3 * c, &r, &a, &b, &t, &e);
+      moments(s, s->lat[c], s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg, s->fr + 3 * c, &r, &a, &b, &t, &e);
       tot[0] += r; tot[1] += r * a; tot[2] += r * b; tot[3] += e;
     }
   memcpy(out, tot, sizeof tot);
@@ -927,6 +1141,18 @@ int pondref_set_state(pondref_state* s, const double* f, const double* g, const 
       for (int i = 0; i < s->Qg; i++) s->g[(size_t)c * s->Qg + i] = g[i * n + k];
       for (int i = 0; i < 3; i++) s->fr[3 * c + i] = frame[i * n + k];
       if (!(s->fr[3 * c + 2] > 0.0)) return fail("frame temperature must be positive");
+    }
+  return 0;
+}
+
+int pondref_get_lattice(const pondref_state* s, int* q, double* theta) {
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  for (int y = 0; y < ny; y++)
+    for (int x = 0; x < nx; x++) {
+      const size_t k = (size_t)x + (size_t)nx * y;
+      const int q1 = s->lat[cidx(s, x, y)];
+      if (q) q[k] = s->D == 2 ? q1 * q1 : q1;
+      if (theta) theta[k] = s->theta[k];
     }
   return 0;
 }

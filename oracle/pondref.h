@@ -26,6 +26,9 @@ extern "C" {
 enum { PONDREF_TF_LAGRANGE = 0, PONDREF_TF_GRAD = 1 };
 enum { PONDREF_BC_PERIODIC = 0, PONDREF_BC_ZERO_GRADIENT = 1, PONDREF_BC_INFLOW = 2 };
 enum { PONDREF_LIM_VANLEER = 0, PONDREF_LIM_MINMOD = 1 };
+/* 2D f-lattice (Sec. III C): D2Q16 everywhere, D2Q9 everywhere, or the
+   multiscale D2Q9/D2Q16 deployment chosen cell by cell (Sec. IV C). */
+enum { PONDREF_F_D2Q16 = 0, PONDREF_F_D2Q9 = 1, PONDREF_F_MULTISCALE = 2 };
 
 typedef struct {
   int dim, nx, ny;          /* ny = 1 when dim = 1 */
@@ -39,6 +42,10 @@ typedef struct {
   double inflow[4][4];      /* rho, u_x, u_y, p per side */
   int limiter;              /* PONDREF_LIM_* */
   int n_corr;               /* face-frame corrector passes */
+  int flat;                 /* PONDREF_F_* (2D only; 0 in 1D) */
+  double ms_threshold;      /* multiscale switch: D2Q16 where the gradient
+                               indicator reaches this value (dilated by two
+                               cells), D2Q9 elsewhere */
 } pondref_config;
 
 typedef struct pondref_state pondref_state;
@@ -79,6 +86,21 @@ int pondref_transform_matrix(int dim, int lattice, int transform, const double s
    full Q x Q moment system of App. B without using the tensor structure. */
 int pondref_transform_matrix_full(int dim, int lattice, const double src[3],
                                   const double dst[3], double* G);
+
+/* Multiscale frame transformation of a 2D f-lattice (Sec. III C): q1s, q1t
+   are the 1D node counts of the source and target lattices (4: D2Q16,
+   3: D2Q9).  Same lattice: Grad's projection of order q1 - 1.  q1s = 3,
+   q1t = 4 (lifting): the D2Q16 expansion whose moments of total order <= 2
+   are those of the D2Q9 populations and whose third-order Hermite moments
+   take their equilibrium value (zero) in the source's comoving frame.
+   q1s = 4, q1t = 3 (projection): Grad's expansion of order 2 from the D2Q16
+   moments.  G is (q1t^2) x (q1s^2), row = target population. */
+int pondref_ms_matrix(int q1s, const double src[3], int q1t, const double dst[3], double* G);
+/* Per cell (row-major [ny][nx]): the f-lattice's population count (16 or 9)
+   and the switch indicator of the last step
+   theta = dx (|grad u| / sqrt(gamma T) + |grad T| / T) (0 when not
+   multiscale).  Either pointer may be NULL. */
+int pondref_get_lattice(const pondref_state* s, int* q, double* theta);
 
 /* One quasi-equilibrium half step on a single cell's f (Qf) and g (Qg),
    written in their comoving frame; kappa = (dt/2)(1/tau1 - 1/tau2). */

@@ -11,13 +11,16 @@ _LIB = None
 
 TF_LAGRANGE, TF_GRAD = 0, 1
 LIM_VANLEER, LIM_MINMOD = 0, 1
+F_D2Q16, F_D2Q9, F_MULTISCALE = 0, 1, 2
+MS_THRESHOLD = 0.05  # default switch threshold of the multiscale deployment
 
 
 class OracleConfig(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("transform", C.c_int),
                 ("gamma", C.c_double), ("tau", C.c_double), ("prandtl", C.c_double),
                 ("cfl", C.c_double), ("dx", C.c_double), ("bc", C.c_int * 4),
-                ("inflow", (C.c_double * 4) * 4), ("limiter", C.c_int), ("n_corr", C.c_int)]
+                ("inflow", (C.c_double * 4) * 4), ("limiter", C.c_int), ("n_corr", C.c_int),
+                ("flat", C.c_int), ("ms_threshold", C.c_double)]
 
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -53,6 +56,8 @@ def load_library():
     lib.pondref_transform_matrix.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
     lib.pondref_transform_matrix_full.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
     lib.pondref_qe_half_step.argtypes = [C.c_int, C.c_double, _dp, _dp]
+    lib.pondref_ms_matrix.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp]
+    lib.pondref_get_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     _LIB = lib
     return lib
 
@@ -63,7 +68,8 @@ def _check(rc):
     return rc
 
 
-def make_config(wl, transform=TF_LAGRANGE, limiter=LIM_VANLEER, n_corr=0) -> OracleConfig:
+def make_config(wl, transform=TF_LAGRANGE, limiter=LIM_VANLEER, n_corr=0, flat=F_D2Q16,
+                ms_threshold=MS_THRESHOLD) -> OracleConfig:
     c = OracleConfig()
     c.dim, c.nx, c.ny = wl.dim, wl.nx, wl.ny
     c.transform = transform
@@ -73,6 +79,7 @@ def make_config(wl, transform=TF_LAGRANGE, limiter=LIM_VANLEER, n_corr=0) -> Ora
         for m in range(4):
             c.inflow[k][m] = float(wl.inflow[k][m])
     c.limiter, c.n_corr = limiter, n_corr
+    c.flat, c.ms_threshold = flat, ms_threshold
     return c
 
 
@@ -109,8 +116,17 @@ def transform_matrix_full(dim, which, src, dst):
     return G.reshape(Q, Q)
 
 
-def cfl_dt(wl) -> float:
-    cfg = make_config(wl)
+def ms_matrix(q1s, src, q1t, dst):
+    """Multiscale frame transformation between 2D f-lattices (q1 = 4: D2Q16,
+    3: D2Q9); rows = target populations."""
+    G = np.zeros(q1t * q1t * q1s * q1s)
+    _check(load_library().pondref_ms_matrix(q1s, np.ascontiguousarray(src, float), q1t,
+                                            np.ascontiguousarray(dst, float), G))
+    return G.reshape(q1t * q1t, q1s * q1s)
+
+
+def cfl_dt(wl, flat=F_D2Q16) -> float:
+    cfg = make_config(wl, flat=flat)
     r, a, b, p = wl.fields()
     return load_library().pondref_cfl_dt(C.byref(cfg), r, a, b, p)
 
@@ -119,10 +135,10 @@ class Oracle:
     """One oracle solve; ``wl`` is an ``inputs.Workload``."""
 
     def __init__(self, wl, transform=TF_LAGRANGE, limiter=LIM_VANLEER, n_corr=0, dt=None,
-                 init=True):
+                 init=True, flat=F_D2Q16, ms_threshold=MS_THRESHOLD):
         self.lib = load_library()
         self.wl = wl
-        self.cfg = make_config(wl, transform, limiter, n_corr)
+        self.cfg = make_config(wl, transform, limiter, n_corr, flat, ms_threshold)
         h = C.c_void_p()
         _check(self.lib.pondref_create(C.byref(self.cfg), C.byref(h)))
         self.h = h
@@ -169,6 +185,14 @@ class Oracle:
         _check(self.lib.pondref_set_state(self.h, np.ascontiguousarray(f, float).reshape(-1),
                                           np.ascontiguousarray(g, float).reshape(-1),
                                           np.ascontiguousarray(fr, float).reshape(-1)))
+
+    def get_lattice(self):
+        """Per cell: f population count (16 or 9) and the last switch indicator."""
+        n = self.nx * self.ny
+        q = np.zeros(n, dtype=np.int32)
+        th = np.zeros(n)
+        _check(self.lib.pondref_get_lattice(self.h, q.ctypes.data, th.ctypes.data))
+        return q.reshape(self.ny, self.nx), th.reshape(self.ny, self.nx)
 
     def get_faces(self):
         nx, ny = self.nx, self.ny
