@@ -55,7 +55,15 @@ enum {
 };
 
 /* f-lattice (the g-lattice is D1Q3 / D2Q9), Table I */
-enum { POND_D1Q4 = 1, POND_D2Q16 = 2 };
+enum { POND_D1Q4 = 1, POND_D2Q16 = 2, POND_D2Q9 = 3, POND_D2Q9_D2Q16 = 4 };
+/* POND_D2Q9: the second-order f-lattice everywhere.  POND_D2Q9_D2Q16: the
+   multiscale deployment (Sec. III C, Sec. IV C) -- each step, D2Q16 within
+   two cells of a cell whose gradient indicator
+   dx (|grad u| / sqrt(gamma T) + |grad T| / T) reaches ms_threshold, D2Q9
+   elsewhere, with the lifting / projection maps between them.  Both need
+   POND_TF_GRAD and dim 2.  With the D2Q9 f-lattice the update does not
+   conserve energy exactly (App. C): a D2Q9 cell takes the energy of its
+   populations. */
 /* POND_MIXED: FP32 populations, transforms and collision; FP64 gauge,
    temperature recovery and conservative flux sums. */
 enum { POND_FP64 = 0, POND_MIXED = 1 };
@@ -69,7 +77,7 @@ enum { POND_LIM_VANLEER = 0, POND_LIM_MINMOD = 1 };
 
 typedef struct {
   int dim, nx, ny;           /* dim 1 or 2; ny = 1 when dim = 1; nx, ny >= 4 (2D), nx >= 4 (1D) */
-  int lattice;               /* POND_D1Q4 (dim 1) or POND_D2Q16 (dim 2) */
+  int lattice;               /* POND_D1Q4 (dim 1); POND_D2Q16, POND_D2Q9 or POND_D2Q9_D2Q16 (dim 2) */
   int transform;             /* POND_TF_* */
   int precision;             /* POND_FP64 or POND_MIXED */
   double gamma;              /* adiabatic exponent, > 1; C_v = 1/(gamma - 1) */
@@ -81,6 +89,7 @@ typedef struct {
   double inflow[4][4];       /* per side (rho, u_x, u_y, p), used where bc = INFLOW */
   int limiter;               /* POND_LIM_* (slopes of the MUSCL reconstruction) */
   int n_corr;                /* face-frame corrector passes, 0..4; 0 = the explicit scheme */
+  double ms_threshold;       /* POND_D2Q9_D2Q16 switch threshold, >= 0 (0.05 is typical) */
 } pond_config;
 
 typedef struct pond_state pond_state;
@@ -132,6 +141,12 @@ int pond_totals_fixed(pond_state* s, int64_t out[8], int* scale_bits);
    doubles, i = i_x + q i_y, nodes ascending), g~ (Qg planes) and the frame
    (u_x, u_y, T planes) they are written in.  Any pointer may be NULL. */
 int pond_export_state(pond_state* s, double* f, double* g, double* frame);
+
+/* Per cell (row-major [ny][nx], host arrays, either may be NULL): the
+   f-lattice's population count the state is written in (16 or 9) and the
+   switch indicator of the last step (zeros unless POND_D2Q9_D2Q16).  Waits
+   for the stream. */
+int pond_lattice_map(pond_state* s, int* q, double* theta);
 
 /* dt in use and the number of steps taken. */
 int pond_get_time(pond_state* s, double* dt, int64_t* nsteps);

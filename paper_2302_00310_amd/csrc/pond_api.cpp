@@ -40,8 +40,14 @@ int validate(const pond_config* c) {
   if (c->dim != 1 && c->dim != 2) return fail(POND_ERR_INVALID, "dim must be 1 or 2");
   if (c->nx < 4 || (c->dim == 2 && c->ny < 4) || (c->dim == 1 && c->ny != 1))
     return fail(POND_ERR_INVALID, "grid needs nx >= 4 and, in 2D, ny >= 4 (ny = 1 in 1D)");
-  if ((c->dim == 1 && c->lattice != POND_D1Q4) || (c->dim == 2 && c->lattice != POND_D2Q16))
-    return fail(POND_ERR_INVALID, "lattice must be D1Q4 in 1D and D2Q16 in 2D");
+  if ((c->dim == 1 && c->lattice != POND_D1Q4) ||
+      (c->dim == 2 && c->lattice != POND_D2Q16 && c->lattice != POND_D2Q9 &&
+       c->lattice != POND_D2Q9_D2Q16))
+    return fail(POND_ERR_INVALID, "lattice must be D1Q4 in 1D and D2Q16, D2Q9 or D2Q9_D2Q16 in 2D");
+  if ((c->lattice == POND_D2Q9 || c->lattice == POND_D2Q9_D2Q16) && c->transform != POND_TF_GRAD)
+    return fail(POND_ERR_INVALID, "the D2Q9 and multiscale f-lattices use Grad's projection");
+  if (c->lattice == POND_D2Q9_D2Q16 && !(c->ms_threshold >= 0.0 && std::isfinite(c->ms_threshold)))
+    return fail(POND_ERR_INVALID, "the multiscale threshold must be finite and >= 0");
   if (c->precision != POND_FP64 && c->precision != POND_MIXED)
     return fail(POND_ERR_INVALID, "unknown precision");
   if (c->transform != POND_TF_LAGRANGE && c->transform != POND_TF_GRAD)
@@ -87,7 +93,11 @@ Layout layout_of(const pond_config* c) {
   L.stage_cells = std::min(L.cells, size_t(kStagingBytes / (8 * L.stage_rows)));
   L.stage_bytes = align256(L.stage_rows * L.stage_cells * 8);
   L.tab_bytes = align256(sizeof(BatchEntry));
-  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.tab_bytes + L.red_bytes + L.stage_bytes;
+  L.ms = c->dim == 2 && (c->lattice == POND_D2Q9 || c->lattice == POND_D2Q9_D2Q16);
+  L.lat_bytes = L.ms ? align256(L.cells) : 0;
+  L.theta_bytes = L.ms ? align256(L.cells * sizeof(double)) : 0;
+  L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.tab_bytes + L.red_bytes + L.stage_bytes +
+            2 * L.lat_bytes + L.theta_bytes;
   return L;
 }
 
@@ -140,6 +150,8 @@ int upload_table(pond_state* s) {
     e.args[par].n_out = s->n[1 - par];
     e.args[par].U_in = s->U[par];
     e.args[par].U_out = s->U[1 - par];
+    e.args[par].lat_in = s->lat[par];
+    e.args[par].lat_out = s->lat[1 - par];
   }
   e.tile_begin = 0;
   e.tiles = s->args.tiles_x * s->args.tiles_y;
@@ -193,7 +205,12 @@ int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, voi
   s->inflow_dev = reinterpret_cast<long long*>(p); p += 256;
   s->tab = reinterpret_cast<BatchEntry*>(p); p += L.tab_bytes;
   s->red = reinterpret_cast<long long*>(p); p += L.red_bytes;
-  s->stage = reinterpret_cast<double*>(p);
+  s->stage = reinterpret_cast<double*>(p); p += L.stage_bytes;
+  if (L.ms) {
+    s->lat[0] = reinterpret_cast<unsigned char*>(p); p += L.lat_bytes;
+    s->lat[1] = reinterpret_cast<unsigned char*>(p); p += L.lat_bytes;
+    s->theta = reinterpret_cast<double*>(p);
+  }
   s->dx = cfg->dx > 0.0 ? cfg->dx : 1.0 / cfg->nx;
   s->cv = 1.0 / (cfg->gamma - 1.0);
   hipError_t e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
@@ -213,7 +230,8 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   const bool twod = c.dim == 2;
   if (twod && !uy) return fail(POND_ERR_INVALID, "uy is required in 2D");
   // dt from the CFL rule at t = 0 (Sec. V): max over cells, nodes and axes
-  // of |sqrt(T) c_ia + u_a|
+  // of |sqrt(T) c_ia + u_a| (largest node of the f-lattice in use)
+  const double cmax = c.lattice == POND_D2Q9 ? kR3 : kB;
   double vmax = 0.0, M = 0.0, U4[4];
   for (size_t k = 0; k < n; ++k) {
     const double vy = twod ? uy[k] : 0.0;
@@ -221,8 +239,8 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
         !std::isfinite(ux[k]) || !std::isfinite(vy))
       return fail(POND_ERR_INVALID, "initial density and pressure must be positive and finite");
     const double rt = std::sqrt(p[k] / rho[k]);
-    vmax = std::max(vmax, std::fabs(ux[k]) + rt * kB);
-    if (twod) vmax = std::max(vmax, std::fabs(vy) + rt * kB);
+    vmax = std::max(vmax, std::fabs(ux[k]) + rt * cmax);
+    if (twod) vmax = std::max(vmax, std::fabs(vy) + rt * cmax);
     conserved_of(rho[k], ux[k], vy, p[k], s->cv, U4);
     for (double v : U4) M = std::max(M, std::fabs(v));
   }
@@ -263,6 +281,13 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
     POND_HIP(hipStreamSynchronize(s->stream));
   }
   POND_HIP(hipMemsetAsync(s->flag, 0, sizeof(int), s->stream));
+  if (s->L.ms) {
+    // D2Q9: every cell on D2Q9; multiscale: D2Q16 until the first switch
+    const int q1 = c.lattice == POND_D2Q9 ? 3 : 4;
+    POND_HIP(hipMemsetAsync(s->lat[0], q1, s->L.lat_bytes, s->stream));
+    POND_HIP(hipMemsetAsync(s->lat[1], q1, s->L.lat_bytes, s->stream));
+    POND_HIP(hipMemsetAsync(s->theta, 0, s->L.theta_bytes, s->stream));
+  }
   POND_HIP(hipStreamSynchronize(s->stream));
   s->cur = 0;
   s->nstep = 0;
@@ -276,6 +301,7 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   a.n_corr = c.n_corr;
   a.limiter = c.limiter;
   a.transform = c.transform;
+  a.ms = s->L.ms ? 1 : 0;
   if (twod) {
     a.tiles_x = (c.nx + kTX2 - 1) / kTX2;
     a.tiles_y = (c.ny + kTY2 - 1) / kTY2;
@@ -310,7 +336,13 @@ int pond_step(pond_state* s, int nsteps) {
   if (!s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
   for (int k = 0; k < nsteps; ++k) {
     if (s->cfg.dim == 2) {
-      POND_HIP(launch_step_batch(s->L.fp64, 1u << s->cfg.transform, s->tab, 1,
+      if (s->cfg.lattice == POND_D2Q9_D2Q16) {
+        // this step's f-lattices, from the state at its start
+        StepArgs a = s->args;
+        POND_HIP(launch_switch(a, s->U[s->cur], s->cfg.ms_threshold, s->cfg.gamma, s->theta,
+                               s->lat[1 - s->cur], s->stream));
+      }
+      POND_HIP(launch_step_batch(s->L.fp64, 1u << kind_of(s->cfg.transform, s->args.ms), s->tab, 1,
                                  s->args.tiles_x * s->args.tiles_y, s->cur, s->stream));
     } else {
       StepArgs a = s->args;
@@ -410,6 +442,30 @@ int pond_export_state(pond_state* s, double* f, double* g, double* frame) {
   return rc;
 }
 
+int pond_lattice_map(pond_state* s, int* q, double* theta) {
+  if (!s || !s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
+  POND_HIP(hipStreamSynchronize(s->stream));
+  const size_t n = s->L.cells;
+  const int q_all = s->cfg.dim == 2 ? 16 : 4;
+  if (q) {
+    if (!s->L.ms) {
+      for (size_t k = 0; k < n; ++k) q[k] = q_all;
+    } else {
+      std::vector<unsigned char> lat(n);
+      POND_HIP(hipMemcpy(lat.data(), s->lat[s->cur], n, hipMemcpyDeviceToHost));
+      for (size_t k = 0; k < n; ++k) q[k] = int(lat[k]) * int(lat[k]);
+    }
+  }
+  if (theta) {
+    if (s->cfg.lattice == POND_D2Q9_D2Q16) {
+      POND_HIP(hipMemcpy(theta, s->theta, n * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      for (size_t k = 0; k < n; ++k) theta[k] = 0.0;
+    }
+  }
+  return POND_OK;
+}
+
 int pond_get_time(pond_state* s, double* dt, int64_t* nsteps) {
   if (!s) return fail(POND_ERR_INVALID, "null state");
   if (dt) *dt = s->dt;
@@ -442,9 +498,13 @@ int pond_save(pond_state* s, const char* path) {
   const size_t elt = s->L.fp64 ? 8 : 4;
   h.pop_bytes = size_t(s->L.NP) * s->L.cells * elt;
   h.led_bytes = 4 * s->L.cells * sizeof(long long);
-  std::vector<char> buf(h.pop_bytes + h.led_bytes);
+  const size_t lat_n = s->L.ms ? s->L.cells : 0;  // f-lattice of each cell (D2Q9 / multiscale)
+  std::vector<char> buf(h.pop_bytes + h.led_bytes + lat_n);
   POND_HIP(hipMemcpy(buf.data(), s->n[s->cur], h.pop_bytes, hipMemcpyDeviceToHost));
   POND_HIP(hipMemcpy(buf.data() + h.pop_bytes, s->U[s->cur], h.led_bytes, hipMemcpyDeviceToHost));
+  if (lat_n)
+    POND_HIP(hipMemcpy(buf.data() + h.pop_bytes + h.led_bytes, s->lat[s->cur], lat_n,
+                       hipMemcpyDeviceToHost));
   FILE* fp = std::fopen(path, "wb");
   if (!fp) return fail(POND_ERR_INVALID, std::string("cannot open ") + path);
   const bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
@@ -462,7 +522,8 @@ int pond_load(pond_state* s, const char* path) {
     std::fclose(fp);
     return fail(POND_ERR_INVALID, "checkpoint does not match this configuration");
   }
-  std::vector<char> buf(h.pop_bytes + h.led_bytes);
+  const size_t lat_n = s->L.ms ? s->L.cells : 0;
+  std::vector<char> buf(h.pop_bytes + h.led_bytes + lat_n);
   const bool ok = std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
   std::fclose(fp);
   if (!ok) return fail(POND_ERR_INVALID, "short read");
@@ -490,6 +551,10 @@ int pond_load(pond_state* s, const char* path) {
   s->cur = 0;
   POND_HIP(hipMemcpy(s->n[0], buf.data(), h.pop_bytes, hipMemcpyHostToDevice));
   POND_HIP(hipMemcpy(s->U[0], buf.data() + h.pop_bytes, h.led_bytes, hipMemcpyHostToDevice));
+  if (lat_n) {
+    POND_HIP(hipMemcpy(s->lat[0], buf.data() + h.pop_bytes + h.led_bytes, lat_n, hipMemcpyHostToDevice));
+    POND_HIP(hipMemcpy(s->lat[1], buf.data() + h.pop_bytes + h.led_bytes, lat_n, hipMemcpyHostToDevice));
+  }
   const int zero = 0;  // a checkpoint holds a healthy state: clear the status flag
   POND_HIP(hipMemcpy(s->flag, &zero, sizeof(int), hipMemcpyHostToDevice));
   return upload_table(s);

@@ -48,6 +48,11 @@ struct StepArgs {
   const long long* U_in;   // 4 planes: rho, rho u_x, rho u_y, rho E (fixed point)
   long long* U_out;
   int* flag;               // bit 1: non-physical state, bit 2: ledger overflow
+  // multiscale f-lattices (per cell, 4 = D2Q16, 3 = D2Q9 nodes per axis):
+  // the lattice n_in is written in, and the one this step uses and writes
+  const unsigned char* lat_in;
+  const unsigned char* lat_out;
+  int ms;                  // 1: per-cell f-lattices (D2Q9 or multiscale)
 };
 
 // One solve of a batched step launch: the arguments of its even and odd
@@ -59,10 +64,17 @@ struct BatchEntry {
 };
 
 // Host-side launchers (defined in pond_kernels.hip).
-// tf_mask: bit t set launches the kernel of transform t (the batch may hold
-// solves with either transform; each kernel skips the other's blocks).
-hipError_t launch_step_batch(bool fp64, unsigned tf_mask, const BatchEntry* tab, int n,
+// Step kernels by kind: transform t (0 Lagrange, 1 Grad) and per-cell
+// f-lattices ms (0: D2Q16 everywhere, 1: D2Q9 or multiscale, Grad only).
+constexpr int kind_of(int transform, int ms) { return transform + 2 * ms; }
+// kind_mask: bit kind_of(t, ms) set launches that kernel (a batch may hold
+// solves of several kinds; each kernel skips the others' blocks).
+hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* tab, int n,
                              int total_tiles, int parity, hipStream_t st);
+// Multiscale switch of one solve: the indicator theta per cell from the
+// ledger's frames, then the f-lattice (4 or 3 nodes per axis) per cell.
+hipError_t launch_switch(const StepArgs& a, const long long* U, double threshold, double gamma,
+                         double* theta, unsigned char* lat_out, hipStream_t st);
 hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
 hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,
                        size_t count, double scale, double cv, void* n, long long* U,

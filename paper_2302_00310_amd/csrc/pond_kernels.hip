@@ -222,45 +222,49 @@ __host__ __device__ constexpr double hermite_node(int a, int k) {
   return a == 0 ? 1.0 : a == 1 ? c : a == 2 ? (c * c - 1.0) / 2.0 : (c * c * c - 3.0 * c) / 6.0;
 }
 
-// Grad's projection of order K = Q1 - 1 into the target frame
-// (eq. GradsProjection; Hermite moments of App. A):
+// Grad's expansion of order K from a source lattice with QS nodes per axis
+// onto a target lattice with QT (eq. GradsProjection; Hermite moments of
+// App. A):
 //   f'_{kn,kt} = W_kn W_kt sum_{a + b <= K} alpha_ab He_a(c_kn) He_b(c_kt) / (a! b!),
 //   alpha_ab = sum_{mn,mt} He_a(x_mn) He_b(y_mt) f_{mn,mt},
-// with x = s c + dn (normal axis) and y = s c + dt (transverse axis); in and
-// out are indexed as in transform_part.  Keeping a + b <= K drops 6 of the 16
-// D2Q16 modes and 3 of the 9 D2Q9 ones, so this map is not the identity when
-// the frames coincide.
-template <int Q1, typename T, int AXIS>
-__device__ __forceinline__ void transform_grad(T s, T dn, T dt, const T* in, T* out) {
-  constexpr int K = Q1 - 1;
-  constexpr int SN = AXIS == 0 ? 1 : Q1, ST = AXIS == 0 ? Q1 : 1;
-  auto herm = [](T x, T (&h)[Q1]) {  // He_0..He_K at x
+// with x = s c + dn (normal axis) and y = s c + dt (transverse axis) the
+// source nodes seen from the target frame; in is indexed mn SN + mt ST over
+// the source lattice, out as kn + QT kt.  QS = QT, K = QS - 1 is Grad's
+// projection of the lattice (keeping a + b <= K drops 6 of the 16 D2Q16
+// modes and 3 of the 9 D2Q9 ones, so it is not the identity when the frames
+// coincide); QS = 4, QT = 3, K = 2 is the multiscale projection; QS = 3,
+// QT = 4, K = 2 with s = 1, d = 0 is the lifting in the source's own frame,
+// where the missing third-order moments take their equilibrium value 0.
+template <int QS, int QT, int K, typename T, int AXIS>
+__device__ __forceinline__ void grad_map(T s, T dn, T dt, const T* in, T* out) {
+  constexpr int SN = AXIS == 0 ? 1 : QS, ST = AXIS == 0 ? QS : 1;
+  auto herm = [](T x, T (&h)[4]) {  // He_0..He_K at x
     const T x2 = x * x;
     h[0] = T(1);
     h[1] = x;
     h[2] = x2 - T(1);
-    if constexpr (Q1 == 4) h[3] = x * (x2 - T(3));
+    if constexpr (K == 3) h[3] = x * (x2 - T(3));
   };
   // beta[mn][b] = sum_mt He_b(y_mt) f[mn][mt], accumulated point by point so
   // that only one point's Hermite values are live
-  T beta[Q1][Q1];
+  T beta[QS][K + 1];
 #pragma unroll
-  for (int mt = 0; mt < Q1; ++mt) {
-    T h[Q1];
-    herm(s * node<Q1, T>(mt) + dt, h);
+  for (int mt = 0; mt < QS; ++mt) {
+    T h[4];
+    herm(s * node<QS, T>(mt) + dt, h);
 #pragma unroll
-    for (int mn = 0; mn < Q1; ++mn) {
+    for (int mn = 0; mn < QS; ++mn) {
       const T f = in[mn * SN + mt * ST];
 #pragma unroll
       for (int b = 0; b <= K; ++b) beta[mn][b] = mt == 0 ? h[b] * f : beta[mn][b] + h[b] * f;
     }
   }
   // alpha[a][b] = sum_mn He_a(x_mn) beta[mn][b], a + b <= K
-  T alpha[Q1][Q1];
+  T alpha[K + 1][K + 1];
 #pragma unroll
-  for (int mn = 0; mn < Q1; ++mn) {
-    T h[Q1];
-    herm(s * node<Q1, T>(mn) + dn, h);
+  for (int mn = 0; mn < QS; ++mn) {
+    T h[4];
+    herm(s * node<QS, T>(mn) + dn, h);
 #pragma unroll
     for (int b = 0; b <= K; ++b) {
 #pragma unroll
@@ -271,23 +275,29 @@ __device__ __forceinline__ void transform_grad(T s, T dn, T dt, const T* in, T* 
   // gamma[kn][b] = W_kn sum_{a <= K - b} He_a(c_kn)/a! alpha[a][b];
   // out[kn][kt] = W_kt sum_b He_b(c_kt)/b! gamma[kn][b]
 #pragma unroll
-  for (int kn = 0; kn < Q1; ++kn) {
-    T gam[Q1];
+  for (int kn = 0; kn < QT; ++kn) {
+    T gam[K + 1];
 #pragma unroll
     for (int b = 0; b <= K; ++b) {
-      T acc = T(hermite_node<Q1>(0, kn)) * alpha[0][b];
+      T acc = T(hermite_node<QT>(0, kn)) * alpha[0][b];
 #pragma unroll
-      for (int a = 1; a + b <= K; ++a) acc += T(hermite_node<Q1>(a, kn)) * alpha[a][b];
-      gam[b] = T(weight<Q1, double>(kn)) * acc;
+      for (int a = 1; a + b <= K; ++a) acc += T(hermite_node<QT>(a, kn)) * alpha[a][b];
+      gam[b] = T(weight<QT, double>(kn)) * acc;
     }
 #pragma unroll
-    for (int kt = 0; kt < Q1; ++kt) {
+    for (int kt = 0; kt < QT; ++kt) {
       T acc = gam[0];
 #pragma unroll
-      for (int b = 1; b <= K; ++b) acc += T(hermite_node<Q1>(b, kt)) * gam[b];
-      out[kn + Q1 * kt] = T(weight<Q1, double>(kt)) * acc;
+      for (int b = 1; b <= K; ++b) acc += T(hermite_node<QT>(b, kt)) * gam[b];
+      out[kn + QT * kt] = T(weight<QT, double>(kt)) * acc;
     }
   }
+}
+
+// Grad's projection of one lattice into the target frame.
+template <int Q1, typename T, int AXIS>
+__device__ __forceinline__ void transform_grad(T s, T dn, T dt, const T* in, T* out) {
+  grad_map<Q1, Q1, Q1 - 1, T, AXIS>(s, dn, dt, in, out);
 }
 
 template <int TF, int Q1, typename T, int AXIS, int K0, int NK>
@@ -373,7 +383,7 @@ __device__ __forceinline__ long long to_fixed(double x, double scale, int* bad) 
 //   f += kappa W_i alpha3 : H3(c_i) / 6,  alpha3 = sum_i f_i H3(c_i);
 //   g += kappa W_i (sum_j g_j c_j) . c_i   (eq. quasi_f, eq. QE_relaxation).
 template <int D, typename T>
-__device__ __forceinline__ void qe_half(T* n, T* m, T kappa) {
+__device__ __forceinline__ void qe_half(T* n, T* m, T kappa, bool with_f = true) {
   if constexpr (D == 1) {
     T a3 = T(0), ag = T(0);
 #pragma unroll
@@ -412,6 +422,8 @@ __device__ __forceinline__ void qe_half(T* n, T* m, T kappa) {
     axxy *= T(3) * k6;
     axyy *= T(3) * k6;
     ayyy *= k6;
+    // a D2Q9 f-lattice carries no third-order moments: only g relaxes
+    if (!with_f) axxx = axxy = axyy = ayyy = T(0);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const T cx = node<4, T>(i & 3), cy = node<4, T>(i >> 2);
@@ -476,6 +488,10 @@ struct Smem {
   T F[G::NP * G::NF];          // face populations phi^{lambda_F}
   double FU[G::NF], FV[G::NF], FRT[G::NF];          // face frames
   int skip;                    // the solve has already failed: leave the tile
+  // per-cell f-lattice (multiscale kernels): 4 = D2Q16, 3 = D2Q9 (nodes per
+  // axis) of the halo slots and of the faces
+  unsigned char Lat[G::NH];
+  unsigned char FL[G::NF];
 };
 
 // Sets `bit` in the solve's status flag if `cond` holds on any active lane of
@@ -555,6 +571,69 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
   for (int i = 0; i < NP; ++i) n[i] = nin[i * a.cells + cell];
 }
 
+// f-lattice of grid cell (gx, gy) for this step (multiscale kernels): the
+// lattice the switch chose for the cell the ghost rule resolves to (an
+// inflow ghost: the next interior cell), and the lattice its stored
+// populations are written in.
+__device__ __forceinline__ void cell_lattice(const StepArgs& a, int gx, int gy, int* q_new,
+                                             int* q_old) {
+  int side = -1;
+  const int sx = resolve(gx, a.nx, a.bc[0], a.bc[1], &side, 0);
+  int sy = gy < 0 ? 0 : (gy >= a.ny ? a.ny - 1 : gy);
+  if (side < 0) sy = resolve(gy, a.ny, a.bc[2], a.bc[3], &side, 2);
+  const size_t cell = size_t(sx) + size_t(a.nx) * size_t(sy);
+  *q_new = a.lat_out[cell];
+  *q_old = side >= 0 ? *q_new : a.lat_in[cell];
+}
+
+// Non-equilibrium populations of a cell moved between f-lattices in the
+// cell's own frame (multiscale switch): lifting keeps the moments to order
+// two and sets the third-order ones to their equilibrium value 0, projection
+// keeps the moments to order two.  The comoving equilibrium rho W maps to
+// rho W exactly either way, so the non-equilibrium part maps on its own.
+template <typename T>
+__device__ __forceinline__ void relattice(T* n, int q_old, int q_new) {
+  if (q_old == q_new) return;
+  T t[16];
+  if (q_new == 4) {
+    grad_map<3, 4, 2, T, 0>(T(1), T(0), T(0), n, t);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) n[i] = t[i];
+  } else {
+    grad_map<4, 3, 2, T, 0>(T(1), T(0), T(0), n, t);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) n[i] = t[i];
+  }
+}
+
+// A stencil cell of a multiscale face: the f populations in LDS slot h
+// (f-lattice sm.Lat[h]) in the face frame and on the face's f-lattice Q1T --
+// Grad's projection when the lattices agree, lifting (own-frame expansion
+// onto D2Q16, then D2Q16 Grad) or projection (D2Q16 -> D2Q9) otherwise.
+// out is indexed n + Q1T t (n normal, t transverse).
+template <int Q1T, typename T, int AXIS>
+__device__ __forceinline__ void ms_stencil(const Smem<2, T>& sm, int h, T s, T dn, T dt, T* out) {
+  using G = Geo<2>;
+  if (sm.Lat[h] == 4) {
+    T in[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) in[i] = sm.P[i * G::NH + h];
+    if constexpr (Q1T == 4) grad_map<4, 4, 3, T, AXIS>(s, dn, dt, in, out);
+    else grad_map<4, 3, 2, T, AXIS>(s, dn, dt, in, out);
+  } else {
+    T in[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) in[i] = sm.P[i * G::NH + h];
+    if constexpr (Q1T == 4) {
+      T l[16];
+      grad_map<3, 4, 2, T, 0>(T(1), T(0), T(0), in, l);
+      grad_map<4, 4, 3, T, AXIS>(s, dn, dt, l, out);
+    } else {
+      grad_map<3, 3, 2, T, AXIS>(s, dn, dt, in, out);
+    }
+  }
+}
+
 // --------------------------------------------------------------------------
 // One face: populations phi^{lambda_F}(x_b, t + dt/2) and the conserved flux.
 // Stencil slots: 0 L, 1 R, 2 L-e_a, 3 R+e_a, 4 L+e_t, 5 L-e_t, 6 R+e_t, 7 R-e_t.
@@ -570,7 +649,7 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
 // operands of the two limiters are selected per population, so each
 // population costs one normal and one transverse limiter; ties take a second
 // pass.
-template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM, int TF>
+template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM, int TF, bool MSF = false>
 __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>& sm,
                                             const int (&st)[Geo<D>::NS], int plane0, double rtF,
                                             double irtF, double uF, double vF, T* bar) {
@@ -583,16 +662,27 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
     // hoisted above the work of the previous one
     asm volatile("" ::: "memory");
     const int h = st[slot];
-    T in[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
-    if constexpr (D == 2) {
+    if constexpr (D == 2 && MSF) {
+      // f of a multiscale face: the cell's own f-lattice onto the face's
       const T s = T(sm.RT[h] * irtF);
       const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
       const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
-      xform<TF, Q1, T, AXIS, K0, NK>(s, dn, dt, in, out);
+      T all[Q1 * Q1];
+      ms_stencil<Q1, T, AXIS>(sm, h, s, dn, dt, all);
+#pragma unroll
+      for (int j = 0; j < Q1 * NK; ++j) out[j] = all[j + Q1 * K0];
     } else {
-      transform<1, Q1, T, TF>(sm.RT[h], sm.U[h], 0.0, irtF, uF, 0.0, in, out);
+      T in[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
+      if constexpr (D == 2) {
+        const T s = T(sm.RT[h] * irtF);
+        const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
+        const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
+        xform<TF, Q1, T, AXIS, K0, NK>(s, dn, dt, in, out);
+      } else {
+        transform<1, Q1, T, TF>(sm.RT[h], sm.U[h], 0.0, irtF, uF, 0.0, in, out);
+      }
     }
     // keep the scheduler from overlapping the stencil cells' transforms
     // (each one holds its own LDS loads and coefficients in registers)
@@ -695,7 +785,7 @@ __device__ __forceinline__ bool tied(double rtF, double uF, double vF) {
 // running limiter operands, so the frame-dependent coefficients of a cell are
 // formed once per face rather than once per transverse row.  Faces where a
 // population's normal velocity falls in the tie band take the row-wise path.
-template <int Q1, typename T, int AXIS, int LIM, int TF>
+template <int Q1, typename T, int AXIS, int LIM, int TF, bool MSF = false>
 __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& sm,
                                                  const int (&st)[Geo<2>::NS], int plane0,
                                                  int fidx, double rtF, double irtF, double uF,
@@ -708,13 +798,17 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
     __builtin_amdgcn_sched_barrier(0);
     asm volatile("" ::: "memory");
     const int h = st[slot];
-    T in[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
     const T s = T(sm.RT[h] * irtF);
     const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
     const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
-    xform<TF, Q1, T, AXIS, 0, Q1>(s, dn, dt, in, o);
+    if constexpr (MSF) {
+      ms_stencil<Q1, T, AXIS>(sm, h, s, dn, dt, o);  // f of a multiscale face
+    } else {
+      T in[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) in[i] = sm.P[(plane0 + i) * G::NH + h];
+      xform<TF, Q1, T, AXIS, 0, Q1>(s, dn, dt, in, o);
+    }
     // the empty asm pins the finished outputs: without it the compiler sinks
     // parts of the transform into the consumers and keeps its operands live
     // across the next cells (spills)
@@ -774,13 +868,16 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
   for (int j = 0; j < Q; ++j) out[j] = park(j) + S[j];
 }
 
-template <int D, typename T, int AXIS, int LIM, int TF>
+template <int D, typename T, int AXIS, int LIM, int TF, bool MS = false>
 __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG;
   // each lattice is reconstructed whole unless a tie needs the row-wise path
   constexpr bool kWhole = true;
   const int hL = st[0], hR = st[1];
+  // f-lattice of the face: the higher one of its two cells (multiscale)
+  bool f16 = true;
+  if constexpr (MS) f16 = max(sm.Lat[hL], sm.Lat[hR]) == 4;
   // eq. AvgFrame
   double uF = 0.5 * (sm.U[hL] + sm.U[hR]);
   double vF = D == 2 ? 0.5 * (sm.V[hL] + sm.V[hR]) : 0.0;
@@ -808,10 +905,52 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
         sm.F[i * G::NF + fidx] = bar[j];
       }
     };
+    if constexpr (D == 2 && MS) {
+      if (!f16) {
+        // D2Q9 f-lattice at this face: 3 x 3 populations in planes 0..8
+        T bar[9];
+        if (!tied<3, AXIS>(rtF, uF, vF)) {
+          reconstruct_full<3, T, AXIS, LIM, TF, true>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
+        } else {
+          static_for<0, 3>([&](auto part) {
+            constexpr int K0 = decltype(part)::value;
+            reconstruct<D, 3, T, AXIS, K0, 1, LIM, TF, true>(a, sm, st, 0, rtF, irtF, uF, vF,
+                                                             bar + 3 * K0);
+          });
+        }
+        const double un = AXIS == 0 ? uF : vF, ut = AXIS == 0 ? vF : uF;
+        double C[3] = {0.0, 0.0, 0.0}, mn = 0.0, mt = 0.0, e2 = 0.0;
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+          double R = 0.0;
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const double fb = double(bar[n + 3 * t]);
+            R += fb;
+            C[t] += fb;
+            sm.F[(AXIS == 0 ? n + 3 * t : t + 3 * n) * G::NF + fidx] = bar[n + 3 * t];
+          }
+          const double vn = rtF * node<3, double>(n) + un;
+          m0 += R;
+          mn += vn * R;
+          e2 += vn * vn * R;
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const double vt = rtF * node<3, double>(t) + ut;
+          mt += vt * C[t];
+          e2 += vt * vt * C[t];
+        }
+        mx += AXIS == 0 ? mn : mt;
+        my += AXIS == 0 ? mt : mn;
+        e += 0.5 * e2;
+      }
+    }
     if constexpr (D == 2) {
-      if (kWhole && !tied<4, AXIS>(rtF, uF, vF)) {
+      if (!f16) {
+      } else if (kWhole && !tied<4, AXIS>(rtF, uF, vF)) {
         T bar[QF];
-        reconstruct_full<4, T, AXIS, LIM, TF>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
+        reconstruct_full<4, T, AXIS, LIM, TF, MS>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
         // moments through row sums R_n (over t) and column sums C_t (over n)
         const double un = AXIS == 0 ? uF : vF, ut = AXIS == 0 ? vF : uF;
         double C[4] = {0.0, 0.0, 0.0, 0.0}, mn = 0.0, mt = 0.0, e2 = 0.0;
@@ -844,7 +983,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
         static_for<0, 4>([&](auto part) {
           constexpr int K0 = decltype(part)::value;
           T bar[4];
-          reconstruct<D, 4, T, AXIS, K0, 1, LIM, TF>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
+          reconstruct<D, 4, T, AXIS, K0, 1, LIM, TF, MS>(a, sm, st, 0, rtF, irtF, uF, vF, bar);
           take_f(bar, K0, 1);
         });
       }
@@ -901,7 +1040,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
     // not separable: the map applied to the comoving rho W (and g's)
     const T dn = T(((AXIS == 0 ? ub : vb) - (AXIS == 0 ? uF : vF)) * irtF);
     const T dt = T(((AXIS == 0 ? vb : ub) - (AXIS == 0 ? vF : uF)) * irtF);
-    {
+    if (f16) {
       T w[QF], eq[QF];
       const T r = T(rho_b);
 #pragma unroll
@@ -911,6 +1050,18 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
       for (int j = 0; j < QF; ++j) {
         const int n = j % 4, t = j / 4;
         T& slot = sm.F[(AXIS == 0 ? n + 4 * t : t + 4 * n) * G::NF + fidx];
+        slot = c1 * slot + c2 * eq[j];
+      }
+    } else {
+      T w[9], eq[9];
+      const T r = T(rho_b);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) w[i] = r * wg<D, T>(i);
+      transform_grad<3, T, AXIS>(sb, dn, dt, w, eq);
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const int n = j % 3, t = j / 3;
+        T& slot = sm.F[(AXIS == 0 ? n + 3 * t : t + 3 * n) * G::NF + fidx];
         slot = c1 * slot + c2 * eq[j];
       }
     }
@@ -954,6 +1105,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
     }
   }
   raise_flag(a.flag, !(rho_b > 0.0) || !(Tb > 0.0), 1);
+  if constexpr (MS) sm.FL[fidx] = f16 ? 4 : 3;
   sm.FU[fidx] = uF;
   sm.FV[fidx] = vF;
   sm.FRT[fidx] = rtF;
@@ -963,7 +1115,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
 // times the normal particle velocity in the face frame, App. C), in FP64,
 // times dt/dx and rounded once to the ledger unit.  Both cells next to a face
 // evaluate it from the same LDS data, so they apply the same integer.
-template <int D, typename T, int AXIS>
+template <int D, typename T, int AXIS, bool MS = false>
 __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& sm, int fi,
                                           long long (&psi)[4]) {
   using G = Geo<D>;
@@ -979,17 +1131,43 @@ __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& s
 #pragma unroll
     for (int k = 0; k < 4; ++k) vt[k] = rtF * node<4, double>(k) + ut;
     double Fn = 0.0, Ft = 0.0;
+    // f on a D2Q9 face (multiscale): nodes of D1Q3, three rows
+    bool f9 = false;
+    if constexpr (MS) f9 = sm.FL[fi] == 3;
+    if (f9) {
+      double vt3[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) vt3[k] = rtF * node<3, double>(k) + ut;
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const double vn = rtF * node<3, double>(n) + un;
+        double R = 0.0, Y = 0.0, Y2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const double f = double(sm.F[(AXIS == 0 ? n + 3 * t : t + 3 * n) * G::NF + fi]);
+          R += f;
+          Y += vt3[t] * f;
+          Y2 += vt3[t] * vt3[t] * f;
+        }
+        Fr += vn * R;
+        Fn += vn * vn * R;
+        Ft += vn * Y;
+        FE += 0.5 * vn * (vn * vn * R + Y2);
+      }
+    }
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const double vn = rtF * node<4, double>(n) + un;
       double R = 0.0, Y = 0.0, Y2 = 0.0;
+      if (!f9) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int i = AXIS == 0 ? n + 4 * t : t + 4 * n;
-        const double f = double(sm.F[i * G::NF + fi]);
-        R += f;
-        Y += vt[t] * f;
-        Y2 += vt[t] * vt[t] * f;
+        for (int t = 0; t < 4; ++t) {
+          const int i = AXIS == 0 ? n + 4 * t : t + 4 * n;
+          const double f = double(sm.F[i * G::NF + fi]);
+          R += f;
+          Y += vt[t] * f;
+          Y2 += vt[t] * vt[t] * f;
+        }
       }
       double Rg = 0.0;
       if (n < 3) {
@@ -1070,10 +1248,155 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
   }
 }
 
+// gather_faces for a cell of a multiscale solve whose f-lattice is qc: each
+// face's f populations (f-lattice sm.FL) go into the cell frame and onto the
+// cell's lattice -- Grad's projection of the lattice, or the D2Q16 -> D2Q9
+// projection where a D2Q16 face borders a D2Q9 cell (a D2Q16 cell only
+// borders D2Q16 faces).  A D2Q9 cell uses f entries 0..8 of acc.
+template <typename T, int AXIS, int TF>
+__device__ __forceinline__ void gather_faces_ms(Smem<2, T>& sm, int flo, int fhi, const Frame& c,
+                                                int qc, T (&acc)[Geo<2>::NP]) {
+  using G = Geo<2>;
+  constexpr int QF = G::QF, QG = G::QG;
+  T dlt[G::NP];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int fi = side ? fhi : flo;
+    const double rtF = sm.FRT[fi], uF = sm.FU[fi], vF = sm.FV[fi];
+    T out[QF];
+    if (qc == 4) {
+      T in[QF];
+#pragma unroll
+      for (int i = 0; i < QF; ++i) in[i] = sm.F[i * G::NF + fi];
+      transform<2, 4, T, TF>(rtF, uF, vF, c.irt, c.ux, c.uy, in, out);
+    } else if (sm.FL[fi] == 4) {
+      T in[QF];
+#pragma unroll
+      for (int i = 0; i < QF; ++i) in[i] = sm.F[i * G::NF + fi];
+      const T s = T(rtF * c.irt), dx = T((uF - c.ux) * c.irt), dy = T((vF - c.uy) * c.irt);
+      grad_map<4, 3, 2, T, 0>(s, dx, dy, in, out);
+    } else {
+      T in[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) in[i] = sm.F[i * G::NF + fi];
+      transform<2, 3, T, TF>(rtF, uF, vF, c.irt, c.ux, c.uy, in, out);
+    }
+#pragma unroll
+    for (int i = 0; i < QF; ++i) dlt[i] = side ? out[i] - dlt[i] : out[i];
+    __builtin_amdgcn_sched_barrier(0);
+    T ing[QG], outg[QG];
+#pragma unroll
+    for (int i = 0; i < QG; ++i) ing[i] = sm.F[(QF + i) * G::NF + fi];
+    transform<2, 3, T, TF>(rtF, uF, vF, c.irt, c.ux, c.uy, ing, outg);
+#pragma unroll
+    for (int i = 0; i < QG; ++i) dlt[QF + i] = side ? outg[i] - dlt[QF + i] : outg[i];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const T rt = T(c.rt), u = T(AXIS == 0 ? c.ux : c.uy);
+  if (qc == 4) {
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+      const int k = AXIS == 0 ? (i & 3) : (i >> 2);
+      acc[i] += (rt * node<4, T>(k) + u) * dlt[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int k = AXIS == 0 ? (i % 3) : (i / 3);
+      acc[i] += (rt * node<3, T>(k) + u) * dlt[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < QG; ++i) {
+    const int k = AXIS == 0 ? (i % 3) : (i / 3);
+    acc[QF + i] += (rt * node<3, T>(k) + u) * dlt[QF + i];
+  }
+}
+
+// Phase 5 for a cell of a multiscale solve: the same DUGKS update on the
+// cell's own f-lattice q (D2Q9: entries 0..8).  A D2Q9 cell's energy is the
+// energy moment of its updated populations (with the second-order f-lattice
+// the update does not carry the conserved flux of energy exactly, App. C),
+// its mass and momentum stay the ledger's.
+template <typename T, int TF>
+__device__ __forceinline__ void step_update_ms(const StepArgs& a, int x, int y,
+                                               const T (&acc)[Geo<2>::NP], const long long (&dU)[4],
+                                               T kappa) {
+  using G = Geo<2>;
+  constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
+  long long U[4];
+  T own[NP];
+  load_cell<2, T>(a, x, y, U, own);
+  int q, qo;
+  cell_lattice(a, x, y, &q, &qo);
+  relattice(own, qo, q);
+  const Frame f0 = gauge(U, a);  // the frame the populations are written in
+  qe_half<2, T>(own, own + QF, kappa, q == 4);
+  const T b = T(a.b_upd), lam = T(a.lam);
+  const T r = T(f0.rho), rg = T(a.geq * f0.T * f0.rho);
+  T ft[QF], gt[QG];
+  if (q == 4) {
+#pragma unroll
+    for (int i = 0; i < QF; ++i) ft[i] = r * wf<2, T>(i) + b * own[i] - lam * acc[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) ft[i] = r * wg<2, T>(i) + b * own[i] - lam * acc[i];
+  }
+#pragma unroll
+  for (int i = 0; i < QG; ++i) gt[i] = rg * wg<2, T>(i) + b * own[QF + i] - lam * acc[QF + i];
+  long long U2[4];
+#pragma unroll
+  for (int q2 = 0; q2 < 4; ++q2) U2[q2] = U[q2] - dU[q2];
+  if (q == 3) {
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double vx = f0.rt * node<3, double>(i % 3) + f0.ux;
+      const double vy = f0.rt * node<3, double>(i / 3) + f0.uy;
+      e += 0.5 * (vx * vx + vy * vy) * double(ft[i]) + double(gt[i]);
+    }
+    int bad = 0;
+    U2[3] = to_fixed(e, a.scale, &bad);
+    raise_flag(a.flag, bad != 0, 2);
+  }
+  const Frame nf = gauge(U2, a);
+  T n2[NP];
+  __builtin_amdgcn_sched_barrier(0);
+  if (q == 4) transform<2, 4, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
+  else transform<2, 3, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
+  __builtin_amdgcn_sched_barrier(0);
+  transform<2, 3, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, gt, n2 + QF);
+  __builtin_amdgcn_sched_barrier(0);
+  const T r2 = T(nf.rho), rg2 = T(a.geq * nf.T * nf.rho);
+  if (q == 4) {
+#pragma unroll
+    for (int i = 0; i < QF; ++i) n2[i] -= r2 * wf<2, T>(i);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) n2[i] -= r2 * wg<2, T>(i);
+#pragma unroll
+    for (int i = 9; i < QF; ++i) n2[i] = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < QG; ++i) n2[QF + i] -= rg2 * wg<2, T>(i);
+  qe_half<2, T>(n2, n2 + QF, kappa, q == 4);
+  raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
+  bool over = false;
+#pragma unroll
+  for (int q2 = 0; q2 < 4; ++q2) over |= (U2[q2] > (1LL << 62)) || (U2[q2] < -(1LL << 62));
+  raise_flag(a.flag, over, 2);
+  const size_t cell = size_t(x) + size_t(a.nx) * size_t(y);
+  T* nout = static_cast<T*>(a.n_out);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) nout[i * a.cells + cell] = n2[i];
+#pragma unroll
+  for (int q2 = 0; q2 < 4; ++q2) a.U_out[q2 * a.cells + cell] = U2[q2];
+}
+
 // --------------------------------------------------------------------------
 // The fused step kernel.
 // --------------------------------------------------------------------------
-template <int D, typename T, int LIM, int TF>
+template <int D, typename T, int LIM, int TF, bool MS = false>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
@@ -1098,11 +1421,28 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     T n[NP];
     load_cell<D, T>(a, gx, gy, U, n);
     const Frame fr = gauge(U, a);
-    qe_half<D, T>(n, n + QF, kappa);
     const int h = hx + G::HX * hy;
     const T r = T(fr.rho), rg = T(a.geq * fr.T * fr.rho);
+    if constexpr (D == 2 && MS) {
+      // multiscale: the slot's f-lattice for this step; populations stored
+      // on another lattice are lifted or projected first
+      int qn, qo;
+      cell_lattice(a, gx, gy, &qn, &qo);
+      relattice(n, qo, qn);
+      sm.Lat[h] = (unsigned char)qn;
+      qe_half<D, T>(n, n + QF, kappa, qn == 4);
+      if (qn == 4) {
 #pragma unroll
-    for (int i = 0; i < QF; ++i) sm.P[i * G::NH + h] = r * wf<D, T>(i) + apre * n[i];
+        for (int i = 0; i < QF; ++i) sm.P[i * G::NH + h] = r * wf<D, T>(i) + apre * n[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sm.P[i * G::NH + h] = r * wg<D, T>(i) + apre * n[i];
+      }
+    } else {
+      qe_half<D, T>(n, n + QF, kappa);
+#pragma unroll
+      for (int i = 0; i < QF; ++i) sm.P[i * G::NH + h] = r * wf<D, T>(i) + apre * n[i];
+    }
 #pragma unroll
     for (int i = 0; i < QG; ++i) sm.P[(QF + i) * G::NH + h] = rg * wg<D, T>(i) + apre * n[QF + i];
     sm.U[h] = fr.ux;
@@ -1114,9 +1454,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
   // where it is needed, so that nothing of it is held through the face phases
   const int cx = tid % G::TX, cy = tid / G::TX;
   const bool own_in = tid < G::NI && x0 + cx < a.nx && (D == 1 || y0 + cy < a.ny);
+  const int own_slot = cx + 2 + G::HX * (cy + G::OY);
   auto own_frame = [&]() {
     Frame f{};
-    const int h = cx + 2 + G::HX * (cy + G::OY);
+    const int h = own_slot;
     f.ux = sm.U[h];
     f.uy = sm.V[h];
     f.T = sm.RT[h] * sm.RT[h];
@@ -1141,7 +1482,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       st[6] = hL + 1 + G::HX;
       st[7] = hL + 1 - G::HX;
     }
-    face_eval<D, T, 0, LIM, TF>(a, sm, st, tid);
+    face_eval<D, T, 0, LIM, TF, MS>(a, sm, st, tid);
   }
   __syncthreads();
   // ---- 2. west/east faces into the cell frame
@@ -1151,12 +1492,15 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
   long long dU[4] = {0, 0, 0, 0};
   if (tid < G::NI) {
     const int fw = cx + (G::TX + 1) * cy;
-    gather_faces<D, T, 0, TF>(sm, fw, fw + 1, own_frame(), acc);
+    if constexpr (D == 2 && MS)
+      gather_faces_ms<T, 0, TF>(sm, fw, fw + 1, own_frame(), sm.Lat[own_slot], acc);
+    else
+      gather_faces<D, T, 0, TF>(sm, fw, fw + 1, own_frame(), acc);
     long long pw[4], pe[4];
     __builtin_amdgcn_sched_barrier(0);
-    face_flux<D, T, 0>(a, sm, fw, pw);
+    face_flux<D, T, 0, MS>(a, sm, fw, pw);
     __builtin_amdgcn_sched_barrier(0);
-    face_flux<D, T, 0>(a, sm, fw + 1, pe);
+    face_flux<D, T, 0, MS>(a, sm, fw + 1, pe);
 #pragma unroll
     for (int q = 0; q < 4; ++q) dU[q] += pe[q] - pw[q];
   }
@@ -1183,7 +1527,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       st[5] = hS - 1;
       st[6] = hS + G::HX + 1;
       st[7] = hS + G::HX - 1;
-      face_eval<D, T, 1, LIM, TF>(a, sm, st, tid);
+      face_eval<D, T, 1, LIM, TF, MS>(a, sm, st, tid);
     }
     __syncthreads();
     // ---- 4. south/north faces
@@ -1193,18 +1537,25 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     }
     if (tid < G::NI) {
       const int fs = cx + G::TX * cy;
-      gather_faces<D, T, 1, TF>(sm, fs, fs + G::TX, own_frame(), acc);
+      if constexpr (MS)
+        gather_faces_ms<T, 1, TF>(sm, fs, fs + G::TX, own_frame(), sm.Lat[own_slot], acc);
+      else
+        gather_faces<D, T, 1, TF>(sm, fs, fs + G::TX, own_frame(), acc);
       long long ps[4], pn[4];
       __builtin_amdgcn_sched_barrier(0);
-      face_flux<D, T, 1>(a, sm, fs, ps);
+      face_flux<D, T, 1, MS>(a, sm, fs, ps);
       __builtin_amdgcn_sched_barrier(0);
-      face_flux<D, T, 1>(a, sm, fs + G::TX, pn);
+      face_flux<D, T, 1, MS>(a, sm, fs + G::TX, pn);
 #pragma unroll
       for (int q = 0; q < 4; ++q) dU[q] += pn[q] - ps[q];
     }
   }
 
   // ---- 5. DUGKS update, new comoving frame, second QE half step
+  if constexpr (D == 2 && MS) {
+    if (own_in) step_update_ms<T, TF>(a, x0 + cx, y0 + cy, acc, dU, kappa);
+    return;
+  }
   if (own_in) {
     long long U[4];
     T own[NP];
@@ -1272,7 +1623,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // A ragged batch of independent solves in one launch: block b advances tile
 // b - tile_begin of the entry whose tile range holds b.  Each entry carries
 // the arguments of both step parities; step `parity` uses args[parity].
-template <int D, typename T, int TF>
+template <int D, typename T, int TF, bool MS>
 __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
     step_batch_kernel(const BatchEntry* tab, int n, int parity) {
   __shared__ Smem<D, T> sm;
@@ -1285,12 +1636,74 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
   // copied before the first store, so the uniform loads stay scalar
   const StepArgs a = tab[lo].args[parity];
   const int tile = b - tab[lo].tile_begin;
-  // one kernel per transform (each keeps its own register allocation);
-  // blocks of solves that use the other transform leave at once
-  if (a.transform != TF) return;
+  // one kernel per transform and f-lattice mode (each keeps its own
+  // register allocation); blocks of solves of another kind leave at once
+  if (a.transform != TF || (a.ms != 0) != MS) return;
   // the limiter is uniform over a solve: one straight-line body per kind
-  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD, TF>(a, tile, sm);
-  else step_tile<D, T, LIM_VANLEER, TF>(a, tile, sm);
+  if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD, TF, MS>(a, tile, sm);
+  else step_tile<D, T, LIM_VANLEER, TF, MS>(a, tile, sm);
+}
+
+// --------------------------------------------------------------------------
+// Multiscale switch (Sec. IV C): D2Q16 where the velocity and temperature
+// gradients are steep, D2Q9 elsewhere.  Indicator per cell, from central
+// differences of the frames (ghosts by the boundary rules, an inflow ghost
+// has the inflow state's frame):
+//   theta = dx (|grad u| / sqrt(gamma T) + |grad T| / T),
+// then D2Q16 within two cells (Chebyshev distance) of a cell with
+// theta >= threshold; off the grid a periodic axis wraps and the other
+// sides take the nearest interior cell.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ Frame frame_at(const StepArgs& a, const long long* U, int gx, int gy) {
+  int side = -1;
+  const int sx = resolve(gx, a.nx, a.bc[0], a.bc[1], &side, 0);
+  int sy = gy;
+  if (side < 0) sy = resolve(gy, a.ny, a.bc[2], a.bc[3], &side, 2);
+  long long u[4];
+  if (side >= 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = a.inflow[4 * side + q];
+  } else {
+    const size_t cell = size_t(sx) + size_t(a.nx) * size_t(sy);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = U[q * a.cells + cell];
+  }
+  return gauge(u, a);
+}
+
+__global__ void switch_theta_kernel(StepArgs a, const long long* U, double gamma, double* theta) {
+  const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= a.cells) return;
+  const int x = int(k % size_t(a.nx)), y = int(k / size_t(a.nx));
+  const Frame xp = frame_at(a, U, x + 1, y), xm = frame_at(a, U, x - 1, y);
+  const Frame yp = frame_at(a, U, x, y + 1), ym = frame_at(a, U, x, y - 1);
+  const Frame c = frame_at(a, U, x, y);
+  const double uxx = 0.5 * (xp.ux - xm.ux), uyx = 0.5 * (xp.uy - xm.uy);
+  const double uxy = 0.5 * (yp.ux - ym.ux), uyy = 0.5 * (yp.uy - ym.uy);
+  const double Tx = 0.5 * (xp.T - xm.T), Ty = 0.5 * (yp.T - ym.T);
+  const double gu = sqrt(uxx * uxx + uyx * uyx + uxy * uxy + uyy * uyy);
+  const double gT = sqrt(Tx * Tx + Ty * Ty);
+  theta[k] = gu / sqrt(gamma * c.T) + gT / c.T;
+}
+
+__global__ void switch_lattice_kernel(StepArgs a, const double* theta, double threshold,
+                                      unsigned char* lat) {
+  const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= a.cells) return;
+  const int x = int(k % size_t(a.nx)), y = int(k / size_t(a.nx));
+  bool hi = false;
+  for (int j = -2; j <= 2; ++j) {
+    for (int i = -2; i <= 2; ++i) {
+      // the ghost rule of the populations: x first; past an inflow side
+      // the nearest interior cell, without wrapping y
+      int side = -1;
+      const int sx = resolve(x + i, a.nx, a.bc[0], a.bc[1], &side, 0);
+      int sy = y + j < 0 ? 0 : (y + j >= a.ny ? a.ny - 1 : y + j);
+      if (side < 0) sy = resolve(y + j, a.ny, a.bc[2], a.bc[3], &side, 2);
+      hi |= theta[size_t(sx) + size_t(a.nx) * size_t(sy)] >= threshold;
+    }
+  }
+  lat[k] = hi ? 4 : 3;
 }
 
 // --------------------------------------------------------------------------
@@ -1387,17 +1800,29 @@ hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_step_batch(bool fp64, unsigned tf_mask, const BatchEntry* tab, int n,
+hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* tab, int n,
                              int total_tiles, int parity, hipStream_t st) {
   const dim3 grid(total_tiles), block(kThreads);
-  if (tf_mask & (1u << TF_LAGRANGE)) {
-    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_LAGRANGE>), grid, block, 0, st, tab, n, parity);
-    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_LAGRANGE>), grid, block, 0, st, tab, n, parity);
+  if (kind_mask & (1u << kind_of(TF_LAGRANGE, 0))) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_LAGRANGE, false>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_LAGRANGE, false>), grid, block, 0, st, tab, n, parity);
   }
-  if (tf_mask & (1u << TF_GRAD)) {
-    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD>), grid, block, 0, st, tab, n, parity);
-    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD>), grid, block, 0, st, tab, n, parity);
+  if (kind_mask & (1u << kind_of(TF_GRAD, 0))) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, false>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, false>), grid, block, 0, st, tab, n, parity);
   }
+  if (kind_mask & (1u << kind_of(TF_GRAD, 1))) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, true>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, true>), grid, block, 0, st, tab, n, parity);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_switch(const StepArgs& a, const long long* U, double threshold, double gamma,
+                         double* theta, unsigned char* lat_out, hipStream_t st) {
+  const dim3 grid(unsigned((a.cells + 255) / 256)), block(256);
+  hipLaunchKernelGGL(switch_theta_kernel, grid, block, 0, st, a, U, gamma, theta);
+  hipLaunchKernelGGL(switch_lattice_kernel, grid, block, 0, st, a, theta, threshold, lat_out);
   return hipGetLastError();
 }
 

@@ -113,7 +113,7 @@ struct pond_server {
   // graph cache for the current resident set: key = (K, parity of the first step)
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   int n_tab = 0, total_tiles = 0, phase = 0;
-  unsigned tf_mask = 0;  // transforms present in the resident set (bit per transform)
+  unsigned tf_mask = 0;  // step-kernel kinds present in the resident set (bit per kind_of)
   // counters for pond_server_stats (written by the server thread under mu)
   double st_admit = 0.0, st_table = 0.0, st_capture = 0.0, st_retire = 0.0;
   double st_cell_updates = 0.0, st_chunks = 0.0, st_changes = 0.0, st_captures = 0.0;
@@ -169,7 +169,7 @@ int upload_table(pond_server* S) {
   S->n_tab = int(S->active.size());
   S->total_tiles = tile;
   S->tf_mask = 0;
-  for (Job* j : S->active) S->tf_mask |= 1u << j->cfg.transform;
+  for (Job* j : S->active) S->tf_mask |= 1u << kind_of(j->cfg.transform, 0);
   S->phase = 0;
   hipError_t err = hipMemcpyAsync(S->dev_tab, S->host_tab, sizeof(BatchEntry) * S->n_tab,
                                   hipMemcpyHostToDevice, S->stream);
@@ -404,6 +404,8 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   int rc = validate(&c);
   if (rc) return rc;
   if (c.dim != 2) return fail(POND_ERR_UNSUPPORTED, "serving runs 2D solves");
+  if (c.lattice != POND_D2Q16)
+    return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 f-lattice");
   if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");

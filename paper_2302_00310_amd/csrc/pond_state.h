@@ -21,6 +21,8 @@ struct Layout {
   size_t pop_bytes = 0, led_bytes = 0, red_bytes = 0, stage_bytes = 0, tab_bytes = 0;
   size_t stage_rows = 0, stage_cells = 0;
   int red_blocks = 256;
+  bool ms = false;                 // per-cell f-lattices (D2Q9 or multiscale)
+  size_t lat_bytes = 0, theta_bytes = 0;
   size_t total = 0;
 };
 
@@ -43,6 +45,8 @@ struct pond_state {
   pond::BatchEntry* tab = nullptr;        // one-entry step table (2D): the kernel serving uses
   long long* red = nullptr;
   double* stage = nullptr;
+  unsigned char* lat[2] = {nullptr, nullptr};  // f-lattice per cell of n[0], n[1]
+  double* theta = nullptr;                     // multiscale switch indicator
   int cur = 0;
   int64_t nstep = 0;
   bool initialized = false;

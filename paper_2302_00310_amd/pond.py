@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpond.so")
 POND_OK, POND_PENDING = 0, 1
 ERRORS = {-1: "POND_ERR_INVALID", -2: "POND_ERR_NOMEM", -3: "POND_ERR_DEVICE",
           -4: "POND_ERR_UNSTABLE", -5: "POND_ERR_REJECTED", -6: "POND_ERR_UNSUPPORTED"}
-POND_D1Q4, POND_D2Q16 = 1, 2
+POND_D1Q4, POND_D2Q16, POND_D2Q9, POND_D2Q9_D2Q16 = 1, 2, 3, 4
 POND_FP64, POND_MIXED = 0, 1
 POND_TF_LAGRANGE, POND_TF_GRAD = 0, 1
 POND_BC_PERIODIC, POND_BC_ZERO_GRADIENT, POND_BC_INFLOW = 0, 1, 2
@@ -36,7 +36,7 @@ class pond_config(C.Structure):
                 ("transform", C.c_int), ("precision", C.c_int), ("gamma", C.c_double),
                 ("tau", C.c_double), ("prandtl", C.c_double), ("cfl", C.c_double),
                 ("dx", C.c_double), ("bc", C.c_int * 4), ("inflow", (C.c_double * 4) * 4),
-                ("limiter", C.c_int), ("n_corr", C.c_int)]
+                ("limiter", C.c_int), ("n_corr", C.c_int), ("ms_threshold", C.c_double)]
 
 
 _dbl = C.POINTER(C.c_double)
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "pond_submit": ([vp, C.POINTER(pond_request), C.POINTER(C.c_uint64)], i),
         "pond_poll": ([vp, C.c_uint64, C.POINTER(pond_result)], i),
         "pond_server_stats": ([vp, C.POINTER(C.c_double)], i),
+        "pond_lattice_map": ([vp, C.POINTER(C.c_int), C.POINTER(C.c_double)], i),
         "pond_server_destroy": ([vp], i),
     }
     for name, (args, res) in sig.items():
@@ -102,6 +103,7 @@ def exported_symbols():
     return ["pond_last_error", "pond_state_bytes", "pond_create", "pond_init_fields", "pond_step",
             "pond_moments", "pond_totals", "pond_totals_fixed", "pond_export_state",
             "pond_get_time", "pond_save", "pond_load", "pond_destroy", "pond_lattice_constants",
+            "pond_lattice_map",
             "pond_server_create", "pond_submit", "pond_poll", "pond_server_stats",
             "pond_server_destroy"]
 
@@ -173,6 +175,14 @@ def pond_export_state(h, n: int, qf: int, qg: int):
     return rc, f, g, fr
 
 
+def pond_lattice_map(h, nx: int, ny: int):
+    q = np.zeros(nx * ny, dtype=np.int32)
+    th = np.zeros(nx * ny)
+    check(load_library().pond_lattice_map(h, q.ctypes.data_as(C.POINTER(C.c_int)),
+                                          th.ctypes.data_as(C.POINTER(C.c_double))))
+    return q.reshape(ny, nx), th.reshape(ny, nx)
+
+
 def pond_get_time(h):
     dt = C.c_double()
     ns = C.c_int64()
@@ -200,11 +210,12 @@ def pond_lattice_constants():
 
 # ---- convenience -----------------------------------------------------------
 def make_config(wl, precision=POND_FP64, transform=POND_TF_LAGRANGE, limiter=POND_LIM_VANLEER,
-                n_corr=0) -> pond_config:
-    """pond_config of an ``inputs.Workload``."""
+                n_corr=0, lattice=None, ms_threshold=0.05) -> pond_config:
+    """pond_config of an ``inputs.Workload``; lattice defaults to D1Q4 / D2Q16."""
     c = pond_config()
     c.dim, c.nx, c.ny = wl.dim, wl.nx, wl.ny
-    c.lattice = POND_D1Q4 if wl.dim == 1 else POND_D2Q16
+    c.lattice = lattice if lattice is not None else (POND_D1Q4 if wl.dim == 1 else POND_D2Q16)
+    c.ms_threshold = ms_threshold
     c.transform, c.precision = transform, precision
     c.gamma, c.tau, c.prandtl, c.cfl, c.dx = wl.gamma, wl.tau, wl.prandtl, wl.cfl, wl.dx
     for k in range(4):
@@ -219,10 +230,11 @@ class Solver:
     """One solve on the current torch device and stream."""
 
     def __init__(self, wl, precision=POND_FP64, n_corr=0, limiter=POND_LIM_VANLEER,
-                 transform=POND_TF_LAGRANGE, stream=None, init=True):
+                 transform=POND_TF_LAGRANGE, stream=None, init=True, lattice=None,
+                 ms_threshold=0.05):
         import torch
         self.wl = wl
-        self.cfg = make_config(wl, precision, transform, limiter, n_corr)
+        self.cfg = make_config(wl, precision, transform, limiter, n_corr, lattice, ms_threshold)
         self.bytes = pond_state_bytes(self.cfg)
         if self.bytes == 0:
             load_library()
@@ -243,6 +255,10 @@ class Solver:
         if check_status:
             check(rc)
         return tuple(a.reshape(self.wl.ny, self.wl.nx) for a in out)
+
+    def lattice_map(self):
+        """Per cell: f population count (16 or 9) and the last switch indicator."""
+        return pond_lattice_map(self.h, self.wl.nx, self.wl.ny)
 
     def export_state(self):
         rc, f, g, fr = pond_export_state(self.h, self.n, self.qf, self.qg)
