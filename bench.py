@@ -92,6 +92,8 @@ def parse():
     p.add_argument("--n", type=int, default=2048, help="grid side")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--no-multiscale", action="store_true",
+                   help="skip the multiscale D2Q9/D2Q16 leg")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--serving-requests", type=int, default=64,
                    help="requests of the serving leg (0 skips it)")
@@ -104,10 +106,10 @@ def parse():
     return p.parse_args()
 
 
-def time_path(wl, precision, steps, warmup):
+def time_path(wl, precision, steps, warmup, **solver_kw):
     import torch
     from paper_2302_00310_amd import pond
-    s = pond.Solver(wl, precision=precision)
+    s = pond.Solver(wl, precision=precision, **solver_kw)
     stream = torch.cuda.current_stream()
     s.step(warmup)
     torch.cuda.synchronize()
@@ -122,8 +124,38 @@ def time_path(wl, precision, steps, warmup):
     kern_ms = e0.elapsed_time(e1) / steps
     rc, _ = pond.pond_moments(s.h, s.n)  # surfaces any non-physical state
     pond.check(rc)
+    if solver_kw.get("lattice") == pond.POND_D2Q9_D2Q16:
+        time_path.d2q16_fraction = float((s.lattice_map()[0] == 16).mean())
     s.close()
     return wall, kern_ms
+
+
+def multiscale_leg(steps, warmup):
+    """The multiscale D2Q9/D2Q16 deployment (Grad's projection, switch
+    threshold 0.05) against D2Q16 and D2Q9 everywhere with the same
+    transform (mixed precision), on the Shu-Osher channel 4096 x 1024 and on
+    the advected vortex 2048^2.  The multiscale step includes its two switch
+    kernels."""
+    from paper_2302_00310_amd import inputs, pond
+    res = {}
+    for key, wl, desc in (
+            ("shu_osher_4096x1024", inputs.shu_osher_2d(4096, 1024, steps=1),
+             "Shu-Osher channel 4096x1024, inflow Mach 3 shock into a sinusoidal density field "
+             "with a random phase per row (seed 4)"),
+            ("vortex_2048", inputs.vortex_2d(2048, steps=1),
+             "isentropic vortex advected at Mach 2, 2048^2 periodic (seed 2)")):
+        cells = wl.nx * wl.ny
+        out = {"workload": desc + "; mixed precision, Grad's projection"}
+        for name, kw in (("d2q16", {}), ("d2q9", {"lattice": pond.POND_D2Q9}),
+                         ("multiscale", {"lattice": pond.POND_D2Q9_D2Q16, "ms_threshold": 0.05})):
+            wall, kern = time_path(wl, pond.POND_MIXED, steps, warmup,
+                                   transform=pond.POND_TF_GRAD, **kw)
+            out[name] = {"value": cells * steps / wall, "unit": "cell-updates/s",
+                         "ms_per_step": kern}
+        out["multiscale"]["d2q16_cell_fraction"] = time_path.d2q16_fraction
+        out["multiscale_over_d2q16"] = out["multiscale"]["value"] / out["d2q16"]["value"]
+        res[key] = out
+    return res
 
 
 def cpu_baseline(wl_full, seconds):
@@ -247,6 +279,8 @@ def main():
                        "hbm_frac": BYTES_PER_CELL["fp64"] * cells / (kern_d * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "alu_frac": flops * cells / (kern_d * 1e-3) / 1e12 / VALU_PEAK_TFLOPS}
         out["mixed_over_fp64"] = value / v64
+    if not a.no_multiscale:
+        out["multiscale"] = multiscale_leg(max(1, a.steps // 2), a.warmup)
     if a.serving_requests > 0:
         sizes = tuple(int(v) for v in a.serving_sizes.split(","))
         out["serving"] = serving_leg(a.serving_requests, sizes, a.serving_arena_gb,
