@@ -611,10 +611,10 @@ __device__ __forceinline__ void relattice(T* n, int q_old, int q_new) {
 // Grad's projection when the lattices agree, lifting (own-frame expansion
 // onto D2Q16, then D2Q16 Grad) or projection (D2Q16 -> D2Q9) otherwise.
 // out is indexed n + Q1T t (n normal, t transverse).
-template <int Q1T, typename T, int AXIS>
+template <int Q1T, typename T, int AXIS, int MODE>
 __device__ __forceinline__ void ms_stencil(const Smem<2, T>& sm, int h, T s, T dn, T dt, T* out) {
   using G = Geo<2>;
-  if (sm.Lat[h] == 4) {
+  if (MODE == 4 || (MODE == 1 && sm.Lat[h] == 4)) {
     T in[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) in[i] = sm.P[i * G::NH + h];
@@ -649,7 +649,7 @@ __device__ __forceinline__ void ms_stencil(const Smem<2, T>& sm, int h, T s, T d
 // operands of the two limiters are selected per population, so each
 // population costs one normal and one transverse limiter; ties take a second
 // pass.
-template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM, int TF, bool MSF = false>
+template <int D, int Q1, typename T, int AXIS, int K0, int NK, int LIM, int TF, int MSF = 0>
 __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>& sm,
                                             const int (&st)[Geo<D>::NS], int plane0, double rtF,
                                             double irtF, double uF, double vF, T* bar) {
@@ -668,7 +668,7 @@ __device__ __forceinline__ void reconstruct(const StepArgs& a, const Smem<D, T>&
       const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
       const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
       T all[Q1 * Q1];
-      ms_stencil<Q1, T, AXIS>(sm, h, s, dn, dt, all);
+      ms_stencil<Q1, T, AXIS, MSF>(sm, h, s, dn, dt, all);
 #pragma unroll
       for (int j = 0; j < Q1 * NK; ++j) out[j] = all[j + Q1 * K0];
     } else {
@@ -785,7 +785,7 @@ __device__ __forceinline__ bool tied(double rtF, double uF, double vF) {
 // running limiter operands, so the frame-dependent coefficients of a cell are
 // formed once per face rather than once per transverse row.  Faces where a
 // population's normal velocity falls in the tie band take the row-wise path.
-template <int Q1, typename T, int AXIS, int LIM, int TF, bool MSF = false>
+template <int Q1, typename T, int AXIS, int LIM, int TF, int MSF = 0>
 __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& sm,
                                                  const int (&st)[Geo<2>::NS], int plane0,
                                                  int fidx, double rtF, double irtF, double uF,
@@ -802,7 +802,7 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
     const T dn = T(((AXIS == 0 ? sm.U[h] : sm.V[h]) - (AXIS == 0 ? uF : vF)) * irtF);
     const T dt = T(((AXIS == 0 ? sm.V[h] : sm.U[h]) - (AXIS == 0 ? vF : uF)) * irtF);
     if constexpr (MSF) {
-      ms_stencil<Q1, T, AXIS>(sm, h, s, dn, dt, o);  // f of a multiscale face
+      ms_stencil<Q1, T, AXIS, MSF>(sm, h, s, dn, dt, o);  // f of a multiscale face
     } else {
       T in[Q];
 #pragma unroll
@@ -868,7 +868,9 @@ __device__ __forceinline__ void reconstruct_full(const StepArgs& a, Smem<2, T>& 
   for (int j = 0; j < Q; ++j) out[j] = park(j) + S[j];
 }
 
-template <int D, typename T, int AXIS, int LIM, int TF, bool MS = false>
+// MS: 0 one f-lattice (D2Q16); 1 per-cell f-lattices; 3 / 4 a tile whose
+// cells are all D2Q9 / all D2Q16 in a solve with per-cell lattices.
+template <int D, typename T, int AXIS, int LIM, int TF, int MS = 0>
 __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, const int (&st)[Geo<D>::NS], int fidx) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG;
@@ -877,7 +879,8 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
   const int hL = st[0], hR = st[1];
   // f-lattice of the face: the higher one of its two cells (multiscale)
   bool f16 = true;
-  if constexpr (MS) f16 = max(sm.Lat[hL], sm.Lat[hR]) == 4;
+  if constexpr (MS == 3) f16 = false;
+  if constexpr (MS == 1) f16 = max(sm.Lat[hL], sm.Lat[hR]) == 4;
   // eq. AvgFrame
   double uF = 0.5 * (sm.U[hL] + sm.U[hR]);
   double vF = D == 2 ? 0.5 * (sm.V[hL] + sm.V[hR]) : 0.0;
@@ -910,11 +913,11 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
         // D2Q9 f-lattice at this face: 3 x 3 populations in planes 0..8
         T bar[9];
         if (!tied<3, AXIS>(rtF, uF, vF)) {
-          reconstruct_full<3, T, AXIS, LIM, TF, true>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
+          reconstruct_full<3, T, AXIS, LIM, TF, MS>(a, sm, st, 0, fidx, rtF, irtF, uF, vF, bar);
         } else {
           static_for<0, 3>([&](auto part) {
             constexpr int K0 = decltype(part)::value;
-            reconstruct<D, 3, T, AXIS, K0, 1, LIM, TF, true>(a, sm, st, 0, rtF, irtF, uF, vF,
+            reconstruct<D, 3, T, AXIS, K0, 1, LIM, TF, MS>(a, sm, st, 0, rtF, irtF, uF, vF,
                                                              bar + 3 * K0);
           });
         }
@@ -1105,7 +1108,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
     }
   }
   raise_flag(a.flag, !(rho_b > 0.0) || !(Tb > 0.0), 1);
-  if constexpr (MS) sm.FL[fidx] = f16 ? 4 : 3;
+  if constexpr (MS == 1) sm.FL[fidx] = f16 ? 4 : 3;
   sm.FU[fidx] = uF;
   sm.FV[fidx] = vF;
   sm.FRT[fidx] = rtF;
@@ -1115,7 +1118,7 @@ __device__ __forceinline__ void face_eval(const StepArgs& a, Smem<D, T>& sm, con
 // times the normal particle velocity in the face frame, App. C), in FP64,
 // times dt/dx and rounded once to the ledger unit.  Both cells next to a face
 // evaluate it from the same LDS data, so they apply the same integer.
-template <int D, typename T, int AXIS, bool MS = false>
+template <int D, typename T, int AXIS, int MS = 0>
 __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& sm, int fi,
                                           long long (&psi)[4]) {
   using G = Geo<D>;
@@ -1133,7 +1136,8 @@ __device__ __forceinline__ void face_flux(const StepArgs& a, const Smem<D, T>& s
     double Fn = 0.0, Ft = 0.0;
     // f on a D2Q9 face (multiscale): nodes of D1Q3, three rows
     bool f9 = false;
-    if constexpr (MS) f9 = sm.FL[fi] == 3;
+    if constexpr (MS == 3) f9 = true;
+    if constexpr (MS == 1) f9 = sm.FL[fi] == 3;
     if (f9) {
       double vt3[3];
 #pragma unroll
@@ -1253,9 +1257,10 @@ __device__ __forceinline__ void gather_faces(Smem<D, T>& sm, int flo, int fhi, c
 // cell's lattice -- Grad's projection of the lattice, or the D2Q16 -> D2Q9
 // projection where a D2Q16 face borders a D2Q9 cell (a D2Q16 cell only
 // borders D2Q16 faces).  A D2Q9 cell uses f entries 0..8 of acc.
-template <typename T, int AXIS, int TF>
+template <typename T, int AXIS, int TF, int MODE>
 __device__ __forceinline__ void gather_faces_ms(Smem<2, T>& sm, int flo, int fhi, const Frame& c,
-                                                int qc, T (&acc)[Geo<2>::NP]) {
+                                                int qc_dyn, T (&acc)[Geo<2>::NP]) {
+  const int qc = MODE == 1 ? qc_dyn : MODE;
   using G = Geo<2>;
   constexpr int QF = G::QF, QG = G::QG;
   T dlt[G::NP];
@@ -1269,7 +1274,7 @@ __device__ __forceinline__ void gather_faces_ms(Smem<2, T>& sm, int flo, int fhi
 #pragma unroll
       for (int i = 0; i < QF; ++i) in[i] = sm.F[i * G::NF + fi];
       transform<2, 4, T, TF>(rtF, uF, vF, c.irt, c.ux, c.uy, in, out);
-    } else if (sm.FL[fi] == 4) {
+    } else if (MODE == 1 && sm.FL[fi] == 4) {
       T in[QF];
 #pragma unroll
       for (int i = 0; i < QF; ++i) in[i] = sm.F[i * G::NF + fi];
@@ -1318,7 +1323,7 @@ __device__ __forceinline__ void gather_faces_ms(Smem<2, T>& sm, int flo, int fhi
 // energy moment of its updated populations (with the second-order f-lattice
 // the update does not carry the conserved flux of energy exactly, App. C),
 // its mass and momentum stay the ledger's.
-template <typename T, int TF>
+template <typename T, int TF, int MODE>
 __device__ __forceinline__ void step_update_ms(const StepArgs& a, int x, int y,
                                                const T (&acc)[Geo<2>::NP], const long long (&dU)[4],
                                                T kappa) {
@@ -1330,6 +1335,7 @@ __device__ __forceinline__ void step_update_ms(const StepArgs& a, int x, int y,
   int q, qo;
   cell_lattice(a, x, y, &q, &qo);
   relattice(own, qo, q);
+  if constexpr (MODE != 1) q = MODE;  // the same value: the tile is uniform
   const Frame f0 = gauge(U, a);  // the frame the populations are written in
   qe_half<2, T>(own, own + QF, kappa, q == 4);
   const T b = T(a.b_upd), lam = T(a.lam);
@@ -1396,7 +1402,163 @@ __device__ __forceinline__ void step_update_ms(const StepArgs& a, int x, int y,
 // --------------------------------------------------------------------------
 // The fused step kernel.
 // --------------------------------------------------------------------------
-template <int D, typename T, int LIM, int TF, bool MS = false>
+// Phases 1-5 of a tile (faces, gathers, update) after its halo is loaded.
+// M: the f-lattice mode of the faces (see face_eval).
+template <int D, typename T, int LIM, int TF, int M>
+__device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int tid, int x0, int y0,
+                                          T kappa) {
+  using G = Geo<D>;
+  constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
+  // the thread's own cell (interior slot tid); its frame is read from LDS
+  // where it is needed, so that nothing of it is held through the face phases
+  const int cx = tid % G::TX, cy = tid / G::TX;
+  const bool own_in = tid < G::NI && x0 + cx < a.nx && (D == 1 || y0 + cy < a.ny);
+  const int own_slot = cx + 2 + G::HX * (cy + G::OY);
+  auto own_frame = [&]() {
+    Frame f{};
+    const int h = own_slot;
+    f.ux = sm.U[h];
+    f.uy = sm.V[h];
+    f.T = sm.RT[h] * sm.RT[h];
+    f.rt = sm.RT[h];
+    f.irt = 1.0 / f.rt;
+    return f;
+  };
+
+  // ---- 1. x-faces
+  if (tid < G::NFX) {
+    const int fi = tid % (G::TX + 1), fj = tid / (G::TX + 1);
+    const int hy = fj + G::OY;
+    const int hL = fi + 1 + G::HX * hy;
+    int st[G::NS];
+    st[0] = hL;
+    st[1] = hL + 1;
+    st[2] = hL - 1;
+    st[3] = hL + 2;
+    if constexpr (D == 2) {
+      st[4] = hL + G::HX;
+      st[5] = hL - G::HX;
+      st[6] = hL + 1 + G::HX;
+      st[7] = hL + 1 - G::HX;
+    }
+    face_eval<D, T, 0, LIM, TF, M>(a, sm, st, tid);
+  }
+  __syncthreads();
+  // ---- 2. west/east faces into the cell frame
+  T acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = T(0);
+  long long dU[4] = {0, 0, 0, 0};
+  if (tid < G::NI) {
+    const int fw = cx + (G::TX + 1) * cy;
+    if constexpr (D == 2 && M != 0)
+      gather_faces_ms<T, 0, TF, M>(sm, fw, fw + 1, own_frame(), sm.Lat[own_slot], acc);
+    else
+      gather_faces<D, T, 0, TF>(sm, fw, fw + 1, own_frame(), acc);
+    long long pw[4], pe[4];
+    __builtin_amdgcn_sched_barrier(0);
+    face_flux<D, T, 0, M>(a, sm, fw, pw);
+    __builtin_amdgcn_sched_barrier(0);
+    face_flux<D, T, 0, M>(a, sm, fw + 1, pe);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dU[q] += pe[q] - pw[q];
+  }
+  if constexpr (D == 2) {
+    // park the x-flux in the cell's own output slot (written only by this
+    // thread, read by nobody else this step) while the y-faces use the registers
+    T* nout = static_cast<T*>(a.n_out);
+    const size_t ocell = size_t(x0 + cx) + size_t(a.nx) * size_t(y0 + cy);
+    if (own_in) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) nout[i * a.cells + ocell] = acc[i];
+    }
+    __syncthreads();
+    // ---- 3. y-faces
+    if (tid < G::NFY) {
+      const int fi = tid % G::TX, fj = tid / G::TX;
+      const int hS = (fi + 2) + G::HX * (fj + 1);
+      int st[G::NS];
+      st[0] = hS;
+      st[1] = hS + G::HX;
+      st[2] = hS - G::HX;
+      st[3] = hS + 2 * G::HX;
+      st[4] = hS + 1;
+      st[5] = hS - 1;
+      st[6] = hS + G::HX + 1;
+      st[7] = hS + G::HX - 1;
+      face_eval<D, T, 1, LIM, TF, M>(a, sm, st, tid);
+    }
+    __syncthreads();
+    // ---- 4. south/north faces
+    if (own_in) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) acc[i] = nout[i * a.cells + ocell];
+    }
+    if (tid < G::NI) {
+      const int fs = cx + G::TX * cy;
+      if constexpr (M != 0)
+        gather_faces_ms<T, 1, TF, M>(sm, fs, fs + G::TX, own_frame(), sm.Lat[own_slot], acc);
+      else
+        gather_faces<D, T, 1, TF>(sm, fs, fs + G::TX, own_frame(), acc);
+      long long ps[4], pn[4];
+      __builtin_amdgcn_sched_barrier(0);
+      face_flux<D, T, 1, M>(a, sm, fs, ps);
+      __builtin_amdgcn_sched_barrier(0);
+      face_flux<D, T, 1, M>(a, sm, fs + G::TX, pn);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dU[q] += pn[q] - ps[q];
+    }
+  }
+
+  // ---- 5. DUGKS update, new comoving frame, second QE half step
+  if constexpr (D == 2 && M != 0) {
+    if (own_in) step_update_ms<T, TF, M>(a, x0 + cx, y0 + cy, acc, dU, kappa);
+    return;
+  }
+  if (own_in) {
+    long long U[4];
+    T own[NP];
+    load_cell<D, T>(a, x0 + cx, y0 + cy, U, own);
+    const Frame f0 = gauge(U, a);  // the frame the populations are written in
+    qe_half<D, T>(own, own + QF, kappa);
+    const T b = T(a.b_upd), lam = T(a.lam);
+    const T r = T(f0.rho), rg = T(a.geq * f0.T * f0.rho);
+    T ft[QF], gt[QG];
+#pragma unroll
+    for (int i = 0; i < QF; ++i) ft[i] = r * wf<D, T>(i) + b * own[i] - lam * acc[i];
+#pragma unroll
+    for (int i = 0; i < QG; ++i) gt[i] = rg * wg<D, T>(i) + b * own[QF + i] - lam * acc[QF + i];
+    long long U2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) U2[q] = U[q] - dU[q];
+    const Frame nf = gauge(U2, a);
+    T n2[NP];
+    __builtin_amdgcn_sched_barrier(0);
+    transform<D, 4, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
+    __builtin_amdgcn_sched_barrier(0);
+    transform<D, 3, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, gt, n2 + QF);
+    __builtin_amdgcn_sched_barrier(0);
+    const T r2 = T(nf.rho), rg2 = T(a.geq * nf.T * nf.rho);
+#pragma unroll
+    for (int i = 0; i < QF; ++i) n2[i] -= r2 * wf<D, T>(i);
+#pragma unroll
+    for (int i = 0; i < QG; ++i) n2[QF + i] -= rg2 * wg<D, T>(i);
+    qe_half<D, T>(n2, n2 + QF, kappa);
+    raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) over |= (U2[q] > (1LL << 62)) || (U2[q] < -(1LL << 62));
+    raise_flag(a.flag, over, 2);
+    const size_t cell = size_t(x0 + cx) + size_t(a.nx) * size_t(D == 2 ? y0 + cy : 0);
+    T* nout = static_cast<T*>(a.n_out);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) nout[i * a.cells + cell] = n2[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a.U_out[q * a.cells + cell] = U2[q];
+  }
+}
+
+template <int D, typename T, int LIM, int TF, int MS = 0>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
@@ -1450,152 +1612,20 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     sm.RT[h] = fr.rt;
   }
   __syncthreads();
-  // the thread's own cell (interior slot tid); its frame is read from LDS
-  // where it is needed, so that nothing of it is held through the face phases
-  const int cx = tid % G::TX, cy = tid / G::TX;
-  const bool own_in = tid < G::NI && x0 + cx < a.nx && (D == 1 || y0 + cy < a.ny);
-  const int own_slot = cx + 2 + G::HX * (cy + G::OY);
-  auto own_frame = [&]() {
-    Frame f{};
-    const int h = own_slot;
-    f.ux = sm.U[h];
-    f.uy = sm.V[h];
-    f.T = sm.RT[h] * sm.RT[h];
-    f.rt = sm.RT[h];
-    f.irt = 1.0 / f.rt;
-    return f;
-  };
-
-  // ---- 1. x-faces
-  if (tid < G::NFX) {
-    const int fi = tid % (G::TX + 1), fj = tid / (G::TX + 1);
-    const int hy = fj + G::OY;
-    const int hL = fi + 1 + G::HX * hy;
-    int st[G::NS];
-    st[0] = hL;
-    st[1] = hL + 1;
-    st[2] = hL - 1;
-    st[3] = hL + 2;
-    if constexpr (D == 2) {
-      st[4] = hL + G::HX;
-      st[5] = hL - G::HX;
-      st[6] = hL + 1 + G::HX;
-      st[7] = hL + 1 - G::HX;
+  // phases 1-5; with per-cell f-lattices a tile whose halo is all D2Q9 or
+  // all D2Q16 runs a body specialised to that lattice
+  if constexpr (D == 2 && MS != 0) {
+    bool has16 = false, has9 = false;
+    for (int k = tid; k < G::NH; k += kThreads) {
+      has16 |= sm.Lat[k] == 4;
+      has9 |= sm.Lat[k] == 3;
     }
-    face_eval<D, T, 0, LIM, TF, MS>(a, sm, st, tid);
-  }
-  __syncthreads();
-  // ---- 2. west/east faces into the cell frame
-  T acc[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) acc[i] = T(0);
-  long long dU[4] = {0, 0, 0, 0};
-  if (tid < G::NI) {
-    const int fw = cx + (G::TX + 1) * cy;
-    if constexpr (D == 2 && MS)
-      gather_faces_ms<T, 0, TF>(sm, fw, fw + 1, own_frame(), sm.Lat[own_slot], acc);
-    else
-      gather_faces<D, T, 0, TF>(sm, fw, fw + 1, own_frame(), acc);
-    long long pw[4], pe[4];
-    __builtin_amdgcn_sched_barrier(0);
-    face_flux<D, T, 0, MS>(a, sm, fw, pw);
-    __builtin_amdgcn_sched_barrier(0);
-    face_flux<D, T, 0, MS>(a, sm, fw + 1, pe);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dU[q] += pe[q] - pw[q];
-  }
-  if constexpr (D == 2) {
-    // park the x-flux in the cell's own output slot (written only by this
-    // thread, read by nobody else this step) while the y-faces use the registers
-    T* nout = static_cast<T*>(a.n_out);
-    const size_t ocell = size_t(x0 + cx) + size_t(a.nx) * size_t(y0 + cy);
-    if (own_in) {
-#pragma unroll
-      for (int i = 0; i < NP; ++i) nout[i * a.cells + ocell] = acc[i];
-    }
-    __syncthreads();
-    // ---- 3. y-faces
-    if (tid < G::NFY) {
-      const int fi = tid % G::TX, fj = tid / G::TX;
-      const int hS = (fi + 2) + G::HX * (fj + 1);
-      int st[G::NS];
-      st[0] = hS;
-      st[1] = hS + G::HX;
-      st[2] = hS - G::HX;
-      st[3] = hS + 2 * G::HX;
-      st[4] = hS + 1;
-      st[5] = hS - 1;
-      st[6] = hS + G::HX + 1;
-      st[7] = hS + G::HX - 1;
-      face_eval<D, T, 1, LIM, TF, MS>(a, sm, st, tid);
-    }
-    __syncthreads();
-    // ---- 4. south/north faces
-    if (own_in) {
-#pragma unroll
-      for (int i = 0; i < NP; ++i) acc[i] = nout[i * a.cells + ocell];
-    }
-    if (tid < G::NI) {
-      const int fs = cx + G::TX * cy;
-      if constexpr (MS)
-        gather_faces_ms<T, 1, TF>(sm, fs, fs + G::TX, own_frame(), sm.Lat[own_slot], acc);
-      else
-        gather_faces<D, T, 1, TF>(sm, fs, fs + G::TX, own_frame(), acc);
-      long long ps[4], pn[4];
-      __builtin_amdgcn_sched_barrier(0);
-      face_flux<D, T, 1, MS>(a, sm, fs, ps);
-      __builtin_amdgcn_sched_barrier(0);
-      face_flux<D, T, 1, MS>(a, sm, fs + G::TX, pn);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) dU[q] += pn[q] - ps[q];
-    }
-  }
-
-  // ---- 5. DUGKS update, new comoving frame, second QE half step
-  if constexpr (D == 2 && MS) {
-    if (own_in) step_update_ms<T, TF>(a, x0 + cx, y0 + cy, acc, dU, kappa);
-    return;
-  }
-  if (own_in) {
-    long long U[4];
-    T own[NP];
-    load_cell<D, T>(a, x0 + cx, y0 + cy, U, own);
-    const Frame f0 = gauge(U, a);  // the frame the populations are written in
-    qe_half<D, T>(own, own + QF, kappa);
-    const T b = T(a.b_upd), lam = T(a.lam);
-    const T r = T(f0.rho), rg = T(a.geq * f0.T * f0.rho);
-    T ft[QF], gt[QG];
-#pragma unroll
-    for (int i = 0; i < QF; ++i) ft[i] = r * wf<D, T>(i) + b * own[i] - lam * acc[i];
-#pragma unroll
-    for (int i = 0; i < QG; ++i) gt[i] = rg * wg<D, T>(i) + b * own[QF + i] - lam * acc[QF + i];
-    long long U2[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) U2[q] = U[q] - dU[q];
-    const Frame nf = gauge(U2, a);
-    T n2[NP];
-    __builtin_amdgcn_sched_barrier(0);
-    transform<D, 4, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
-    __builtin_amdgcn_sched_barrier(0);
-    transform<D, 3, T, TF>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, gt, n2 + QF);
-    __builtin_amdgcn_sched_barrier(0);
-    const T r2 = T(nf.rho), rg2 = T(a.geq * nf.T * nf.rho);
-#pragma unroll
-    for (int i = 0; i < QF; ++i) n2[i] -= r2 * wf<D, T>(i);
-#pragma unroll
-    for (int i = 0; i < QG; ++i) n2[QF + i] -= rg2 * wg<D, T>(i);
-    qe_half<D, T>(n2, n2 + QF, kappa);
-    raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
-    bool over = false;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) over |= (U2[q] > (1LL << 62)) || (U2[q] < -(1LL << 62));
-    raise_flag(a.flag, over, 2);
-    const size_t cell = size_t(x0 + cx) + size_t(a.nx) * size_t(D == 2 ? y0 + cy : 0);
-    T* nout = static_cast<T*>(a.n_out);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) nout[i * a.cells + cell] = n2[i];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a.U_out[q * a.cells + cell] = U2[q];
+    const int any16 = __syncthreads_or(has16), any9 = __syncthreads_or(has9);
+    if (!any9) step_body<D, T, LIM, TF, 4>(a, sm, tid, x0, y0, kappa);
+    else if (!any16) step_body<D, T, LIM, TF, 3>(a, sm, tid, x0, y0, kappa);
+    else step_body<D, T, LIM, TF, 1>(a, sm, tid, x0, y0, kappa);
+  } else {
+    step_body<D, T, LIM, TF, 0>(a, sm, tid, x0, y0, kappa);
   }
 }
 
@@ -1623,7 +1653,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // A ragged batch of independent solves in one launch: block b advances tile
 // b - tile_begin of the entry whose tile range holds b.  Each entry carries
 // the arguments of both step parities; step `parity` uses args[parity].
-template <int D, typename T, int TF, bool MS>
+template <int D, typename T, int TF, int MS>
 __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
     step_batch_kernel(const BatchEntry* tab, int n, int parity) {
   __shared__ Smem<D, T> sm;
@@ -1638,7 +1668,7 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
   const int tile = b - tab[lo].tile_begin;
   // one kernel per transform and f-lattice mode (each keeps its own
   // register allocation); blocks of solves of another kind leave at once
-  if (a.transform != TF || (a.ms != 0) != MS) return;
+  if (a.transform != TF || a.ms != MS) return;
   // the limiter is uniform over a solve: one straight-line body per kind
   if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD, TF, MS>(a, tile, sm);
   else step_tile<D, T, LIM_VANLEER, TF, MS>(a, tile, sm);
@@ -1804,16 +1834,16 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
                              int total_tiles, int parity, hipStream_t st) {
   const dim3 grid(total_tiles), block(kThreads);
   if (kind_mask & (1u << kind_of(TF_LAGRANGE, 0))) {
-    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_LAGRANGE, false>), grid, block, 0, st, tab, n, parity);
-    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_LAGRANGE, false>), grid, block, 0, st, tab, n, parity);
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_LAGRANGE, 0>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_LAGRANGE, 0>), grid, block, 0, st, tab, n, parity);
   }
   if (kind_mask & (1u << kind_of(TF_GRAD, 0))) {
-    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, false>), grid, block, 0, st, tab, n, parity);
-    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, false>), grid, block, 0, st, tab, n, parity);
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 0>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 0>), grid, block, 0, st, tab, n, parity);
   }
   if (kind_mask & (1u << kind_of(TF_GRAD, 1))) {
-    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, true>), grid, block, 0, st, tab, n, parity);
-    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, true>), grid, block, 0, st, tab, n, parity);
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 1>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 1>), grid, block, 0, st, tab, n, parity);
   }
   return hipGetLastError();
 }
