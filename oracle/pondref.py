@@ -126,9 +126,14 @@ def ms_matrix(q1s, src, q1t, dst):
 
 
 def cfl_dt(wl, flat=F_D2Q16) -> float:
-    cfg = make_config(wl, flat=flat)
+    """The CFL step of ``wl``'s initial fields on the f-lattice ``flat`` (the
+    D2Q9 f-lattices need Grad's projection, so the config names it)."""
+    cfg = make_config(wl, TF_GRAD if flat != F_D2Q16 else TF_LAGRANGE, flat=flat)
     r, a, b, p = wl.fields()
-    return load_library().pondref_cfl_dt(C.byref(cfg), r, a, b, p)
+    dt = load_library().pondref_cfl_dt(C.byref(cfg), r, a, b, p)
+    if not dt > 0.0:
+        raise RuntimeError("pondref: " + load_library().pondref_last_error().decode())
+    return dt
 
 
 class Oracle:

@@ -36,20 +36,23 @@ def moment_errors(gpu_m, ora_m, l2=False):
     return {"rho": f(r_g, r_o), "u": f(u_g, u_o), "T": f(T_g, T_o)}
 
 
-def window_samples(wl, points, steps, transform=0, n_corr=0, limiter=0):
+def window_samples(wl, points, steps, transform=0, n_corr=0, limiter=0, flat=0,
+                   ms_threshold=0.05, dep=2):
     """Oracle values of (rho, u_x, u_y, T) at the cells ``points`` after
     ``steps`` steps, each computed on a window that contains the cell's whole
-    domain of dependence (two cells per step), started from the same seeded
-    initial fields and advanced with the full grid's dt."""
-    dt = oracle.cfl_dt(wl)
-    R = 2 * steps + 3
+    domain of dependence (``dep`` cells per step: 2 for the FV stencil, 5 with
+    the multiscale switch, whose gradient and dilation add 3), started from
+    the same seeded initial fields and advanced with the full grid's dt."""
+    dt = oracle.cfl_dt(wl, flat=flat)
+    R = dep * steps + 3
     out = []
     for (x, y) in points:
         if wl.dim == 1:
             w, (ox, oy) = inputs.window(wl, x - R, 0, 2 * R + 1, 1)
         else:
             w, (ox, oy) = inputs.window(wl, x - R, y - R, 2 * R + 1, 2 * R + 1)
-        o = oracle.Oracle(w, transform=transform, n_corr=n_corr, limiter=limiter, dt=dt)
+        o = oracle.Oracle(w, transform=transform, n_corr=n_corr, limiter=limiter, dt=dt, flat=flat,
+                          ms_threshold=ms_threshold)
         o.step(steps)
         m = o.moments()
         # position of (x, y) inside the window

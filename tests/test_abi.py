@@ -102,3 +102,16 @@ def test_no_device_is_an_error_not_a_fallback(pond):
     h = C.c_void_p()
     rc = pond.load_library().pond_create(C.byref(c), C.c_void_p(256), 1 << 30, None, C.byref(h))
     assert rc == -3
+
+
+def test_f_lattice_rules(pond):
+    """D2Q9 and multiscale need Grad's projection and 2D; the multiscale
+    threshold must be finite and >= 0; per-cell lattices add two byte
+    planes and an indicator plane to the footprint."""
+    assert pond.pond_state_bytes(_cfg(pond, lattice=3, transform=0)) == 0
+    assert pond.pond_state_bytes(_cfg(pond, lattice=4, transform=0)) == 0
+    assert pond.pond_state_bytes(_cfg(pond, lattice=4, transform=1, ms_threshold=-1.0)) == 0
+    base = pond.pond_state_bytes(_cfg(pond, transform=1))
+    ms = pond.pond_state_bytes(_cfg(pond, lattice=4, transform=1))
+    assert ms >= base + 32 * 32 * (2 + 8)
+    assert pond.pond_state_bytes(_cfg(pond, lattice=3, transform=1)) == ms

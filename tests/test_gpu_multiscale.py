@@ -137,3 +137,37 @@ def test_multiscale_checkpoint_resume_bitwise(pond, tmp_path):
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_multiscale_full_size_shu_osher_sampled_cells(pond, precision):
+    """The 4096 x 1024 Shu-Osher channel with the multiscale deployment, 6
+    steps: sampled cells against the oracle run on a window holding each
+    cell's domain of dependence (5 cells per step)."""
+    from .gpu_common import rel_err, window_samples
+    wl = inputs.shu_osher_2d()
+    steps = 6
+    rng = np.random.Generator(np.random.PCG64(23))
+    pts = [(0, 0), (wl.nx - 1, wl.ny - 1), (wl.nx // 2, wl.ny // 2), (430, 17), (410, 500)]
+    pts += [(int(rng.integers(wl.nx)), int(rng.integers(wl.ny))) for _ in range(3)]
+    ref, dt = window_samples(wl, pts, steps, transform=GRAD, flat=O_MSCALE, dep=5)
+    print("multiscale full size", precision, flush=True)
+    s = pond.Solver(wl, precision=precision, transform=GRAD, lattice=MSCALE, ms_threshold=0.05)
+    try:
+        assert abs(s.dt / dt - 1.0) < 1e-15
+        s.step(steps)
+        m = s.moments()
+        q = s.lattice_map()[0]
+        assert (q == 16).any() and (q == 9).any()
+    finally:
+        s.close()
+    got = np.array([[float(a[y, x]) for a in m] for (x, y) in pts])
+    if precision == FP64:
+        for k in range(4):
+            assert rel_err(got[:, k], ref[:, k], floor=1.0 if k in (1, 2) else 1e-300) <= 1e-12, k
+    else:
+        # the mixed bar as on whole fields: relative L2 of rho, of (u_x, u_y)
+        # jointly and of T over the sampled cells (u_y alone is a small
+        # perturbation, so its own relative error is no measure of precision)
+        e = moment_errors(tuple(got.T), tuple(ref.T), l2=True)
+        assert max(e.values()) <= 1e-5, e
