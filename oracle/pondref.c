@@ -418,7 +418,15 @@ static int check_config(const pondref_config* c) {
     return fail("the multiscale threshold must be >= 0");
   const int nside = c->dim == 2 ? 4 : 2;
   for (int k = 0; k < nside; k++)
-    if (c->bc[k] < 0 || c->bc[k] > 2) return fail("unknown boundary condition");
+    if (c->bc[k] < 0 || c->bc[k] > 3) return fail("unknown boundary condition");
+  for (int k = 0; k < nside; k++) {
+    if (c->bc[k] != PONDREF_BC_WALL) continue;
+    if (c->dim != 2 || c->flat != PONDREF_F_D2Q16) return fail("walls need 2D and the D2Q16 f-lattice");
+    if ((k < 2 ? c->nx : c->ny) < 3) return fail("a wall needs three cells along its normal");
+    if (!(c->wall[k][2] > 0.0) || !isfinite(c->wall[k][0]) || !isfinite(c->wall[k][1]))
+      return fail("a wall needs a positive temperature and a finite velocity");
+    if (c->wall[k][k < 2 ? 0 : 1] != 0.0) return fail("a wall cannot move along its normal");
+  }
   for (int a = 0; a < nside; a += 2)
     if ((c->bc[a] == PONDREF_BC_PERIODIC) != (c->bc[a + 1] == PONDREF_BC_PERIODIC))
       return fail("a periodic axis needs periodic conditions on both sides");
@@ -628,6 +636,136 @@ static int resolve_axis(int v, int n, int bc_lo, int bc_hi, int* side_inflow, in
   return v;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Wall ghosts (Sec. IV D: ghost-node approach with the Chapman-Enskog      */
+/* non-equilibrium of the first order).                                     */
+/* reading: ghost layer k mirrors the k-th cell from the wall: density      */
+/* keeps its value (zero normal gradient), velocity and temperature are     */
+/* reflected about the wall's values (u_G = 2 u_w - u_B, T_G = 2 T_w - T_B). */
+/* The hydrodynamic gradients at a ghost are second-order central           */
+/* differences of this mirror-extended field at the start of the step;      */
+/* along the wall, past the domain, the field wraps on a periodic axis and  */
+/* takes the nearest cell otherwise.                                        */
+/* ------------------------------------------------------------------------ */
+
+/* (rho, u_x, u_y, T) of the extended field at normal index m (m >= 0: the
+   interior cell m rows in from wall `side`; m < 0: ghost layer -m) and
+   coordinate t along the wall */
+static void wall_field(const pondref_state* s, int side, int m, int t, double out[4]) {
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  const int nt = side < 2 ? ny : nx;
+  const int bt = side < 2 ? s->cfg.bc[2] : s->cfg.bc[0];
+  if (t < 0 || t >= nt)
+    t = bt == PONDREF_BC_PERIODIC ? ((t % nt) + nt) % nt : (t < 0 ? 0 : nt - 1);
+  const int mm = m >= 0 ? m : -m - 1;
+  int x, y;
+  switch (side) {
+    case 0: x = mm; y = t; break;
+    case 1: x = nx - 1 - mm; y = t; break;
+    case 2: x = t; y = mm; break;
+    default: x = t; y = ny - 1 - mm; break;
+  }
+  const int c = cidx(s, x, y);
+  const double* f = s->f + (size_t)c * s->Qf;
+  double rho = 0.0;
+  for (int i = 0; i < s->Qf; i++) rho += f[i];
+  out[0] = rho;
+  out[1] = s->fr[3 * c + 0];
+  out[2] = s->fr[3 * c + 1];
+  out[3] = s->fr[3 * c + 2];
+  if (m < 0) {
+    const double* w = s->cfg.wall[side];
+    out[1] = 2.0 * w[0] - out[1];
+    out[2] = 2.0 * w[1] - out[2];
+    out[3] = 2.0 * w[2] - out[3];
+  }
+}
+
+/* Ghost populations: the comoving equilibrium plus the non-equilibrium
+   part whose moments are the Chapman-Enskog ones (Sec. IV D), expanded in
+   Hermite polynomials of c = (v - u_G)/sqrt(T_G) (Grad's projection: order
+   3 for f on D2Q16, order 2 for g on D2Q9).  With p = rho T,
+   S = grad u + (grad u)^T and d = div u:
+     f: P1 = -tau1 p (S - (d / C_v) I), central third moment
+        -tau2 p [dT/dx_a delta_bc]_cyc;
+     g: zeroth moment tau1 (C_v - D/2) p d / C_v, central first moment
+        -tau2 (C_v - D/2) p grad T, central second moment
+        -tau1 (C_v - D/2) p T (S - (2 d / C_v) I).
+   reading: the g moments are re-derived from the first Chapman-Enskog
+   order with g^eq = (C_v - D/2) T rho W (eq. geqPond) and written about
+   the ghost's own velocity (the printed ones carry a factor 2 and a sign
+   of a different normalisation of g).  Then the non-equilibrium parts
+   carry no mass, momentum or energy, the total heat flux is
+   -tau2 C_p p grad T (kappa of Sec. IV) and the stress is that of mu and
+   varsigma.  The stored variable is f~ = f^eq + (1 + dt / (2 tau1)) f^neq
+   (eq. variableTransform with the BGK time of the streaming part). */
+static void wall_ghost(const pondref_state* s, int side, int k, int t, double* f, double* g,
+                       double fr[3]) {
+  double G[4], pn[4], mn[4], pt[4], mt[4];
+  wall_field(s, side, -k, t, G);
+  wall_field(s, side, -k + 1, t, pn);   /* one cell further in */
+  wall_field(s, side, -k - 1, t, mn);   /* one cell further out */
+  wall_field(s, side, -k, t + 1, pt);
+  wall_field(s, side, -k, t - 1, mt);
+  const double h = 0.5 / s->dx;
+  /* m grows inward: along +x or +y on the low sides, against it on the high */
+  const double sn = (side == 0 || side == 2) ? 1.0 : -1.0;
+  /* d/dx_a of (u_x, u_y, T): row a = derivative direction */
+  double A[2][3];
+  for (int q = 0; q < 3; q++) {
+    const double dn = sn * (pn[q + 1] - mn[q + 1]) * h;
+    const double dtg = (pt[q + 1] - mt[q + 1]) * h;
+    if (side < 2) { A[0][q] = dn; A[1][q] = dtg; }
+    else { A[0][q] = dtg; A[1][q] = dn; }
+  }
+  const double rho = G[0], ux = G[1], uy = G[2], T = G[3], p = rho * T;
+  const double Sxx = 2.0 * A[0][0], Syy = 2.0 * A[1][1], Sxy = A[0][1] + A[1][0];
+  const double d = A[0][0] + A[1][1], Tx = A[0][2], Ty = A[1][2];
+  const double cv = s->cv, ce = s->cv - 1.0; /* C_v - D/2, D = 2 */
+  const double t1 = s->tau1, t2 = s->tau2;
+  /* f: Hermite coefficients alpha_ab (a x-indices, b y-indices) */
+  const double Pxx = -t1 * p * (Sxx - d / cv), Pyy = -t1 * p * (Syy - d / cv), Pxy = -t1 * p * Sxy;
+  const double a20 = Pxx / T, a11 = Pxy / T, a02 = Pyy / T;
+  const double T32 = T * sqrt(T);
+  const double a30 = -3.0 * t2 * p * Tx / T32, a21 = -t2 * p * Ty / T32;
+  const double a12 = -t2 * p * Tx / T32, a03 = -3.0 * t2 * p * Ty / T32;
+  /* g: Hermite coefficients */
+  const double b0 = t1 * ce * p * d / cv;
+  const double b1x = -t2 * ce * p * Tx / sqrt(T), b1y = -t2 * ce * p * Ty / sqrt(T);
+  const double M2xx = -t1 * ce * p * T * (Sxx - 2.0 * d / cv);
+  const double M2yy = -t1 * ce * p * T * (Syy - 2.0 * d / cv);
+  const double M2xy = -t1 * ce * p * T * Sxy;
+  const double b20 = M2xx / T - b0, b11 = M2xy / T, b02 = M2yy / T - b0;
+  const double kf = 1.0 + s->dt / (2.0 * t1);
+  for (int i = 0; i < 16; i++) {
+    const double cx = s->cfx[i], cy = s->cfy[i];
+    const double neq = a20 * hermite(2, cx) / 2.0 + a11 * cx * cy + a02 * hermite(2, cy) / 2.0 +
+                       a30 * hermite(3, cx) / 6.0 + a21 * hermite(2, cx) * cy / 2.0 +
+                       a12 * cx * hermite(2, cy) / 2.0 + a03 * hermite(3, cy) / 6.0;
+    f[i] = rho * s->Wf[i] + kf * s->Wf[i] * neq;
+  }
+  for (int i = 0; i < 9; i++) {
+    const double cx = s->cgx[i], cy = s->cgy[i];
+    const double neq = b0 + b1x * cx + b1y * cy + b20 * hermite(2, cx) / 2.0 + b11 * cx * cy +
+                       b02 * hermite(2, cy) / 2.0;
+    g[i] = ce * T * rho * s->Wg[i] + kf * s->Wg[i] * neq;
+  }
+  fr[0] = ux;
+  fr[1] = uy;
+  fr[2] = T;
+}
+
+int pondref_wall_ghost(const pondref_state* s, int side, int layer, int t, double* f, double* g,
+                       double frame[3]) {
+  if (!s || !f || !g || !frame) return fail("null argument");
+  if (s->D != 2 || side < 0 || side > 3 || s->cfg.bc[side] != PONDREF_BC_WALL)
+    return fail("not a wall side");
+  if (layer < 1 || layer > NG) return fail("ghost layer must be 1 or 2");
+  if (t < 0 || t >= (side < 2 ? s->cfg.ny : s->cfg.nx)) return fail("t out of range");
+  wall_ghost(s, side, layer, t, f, g, frame);
+  return 0;
+}
+
 static void fill_ghosts(pondref_state* s) {
   const int nx = s->cfg.nx, ny = s->cfg.ny;
   const int ylo = s->D == 2 ? -NG : 0, yhi = s->D == 2 ? ny + NG : 1;
@@ -640,7 +778,17 @@ static void fill_ghosts(pondref_state* s) {
       if (side < 0 && s->D == 2) sy = resolve_axis(y, ny, s->cfg.bc[2], s->cfg.bc[3], &side, 2);
       const int c = cidx(s, x, y);
       double* fr = s->fr + 3 * c;
-      if (side >= 0) {
+      if (side >= 0 && s->cfg.bc[side] == PONDREF_BC_WALL) {
+        /* wall ghost: layer from the distance to the wall, coordinate along
+           the wall resolved as above (x first) */
+        const int v = side < 2 ? x : y, n = side < 2 ? nx : ny;
+        const int k = v < 0 ? -v : v - n + 1;
+        int t = side < 2 ? y : sx;
+        if (side < 2 && (t < 0 || t >= ny))
+          t = s->cfg.bc[2] == PONDREF_BC_PERIODIC ? ((t % ny) + ny) % ny : (t < 0 ? 0 : ny - 1);
+        s->lat[c] = 4;
+        wall_ghost(s, side, k, t, s->f + (size_t)c * s->Qf, s->g + (size_t)c * s->Qg, fr);
+      } else if (side >= 0) {
         /* reading: an inflow ghost takes the f-lattice of the interior cell
            next to it */
         const int bx = sx, by = s->D == 2 ? (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) : 0;

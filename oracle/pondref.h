@@ -24,7 +24,12 @@ extern "C" {
 #endif
 
 enum { PONDREF_TF_LAGRANGE = 0, PONDREF_TF_GRAD = 1 };
-enum { PONDREF_BC_PERIODIC = 0, PONDREF_BC_ZERO_GRADIENT = 1, PONDREF_BC_INFLOW = 2 };
+/* Walls (Sec. IV D, 2D with the D2Q16 f-lattice): ghost cells mirror the
+   cells next to the wall -- density even, velocity and temperature odd
+   about the wall's values -- and carry the Chapman-Enskog non-equilibrium
+   of the mirrored gradients. */
+enum { PONDREF_BC_PERIODIC = 0, PONDREF_BC_ZERO_GRADIENT = 1, PONDREF_BC_INFLOW = 2,
+       PONDREF_BC_WALL = 3 };
 enum { PONDREF_LIM_VANLEER = 0, PONDREF_LIM_MINMOD = 1 };
 /* 2D f-lattice (Sec. III C): D2Q16 everywhere, D2Q9 everywhere, or the
    multiscale D2Q9/D2Q16 deployment chosen cell by cell (Sec. IV C). */
@@ -46,6 +51,8 @@ typedef struct {
   double ms_threshold;      /* multiscale switch: D2Q16 where the gradient
                                indicator reaches this value (dilated by two
                                cells), D2Q9 elsewhere */
+  double wall[4][3];        /* u_x, u_y, T of the wall per side (used if WALL;
+                               T > 0, no velocity normal to the wall) */
 } pondref_config;
 
 typedef struct pondref_state pondref_state;
@@ -101,6 +108,12 @@ int pondref_ms_matrix(int q1s, const double src[3], int q1t, const double dst[3]
    theta = dx (|grad u| / sqrt(gamma T) + |grad T| / T) (0 when not
    multiscale).  Either pointer may be NULL. */
 int pondref_get_lattice(const pondref_state* s, int* q, double* theta);
+
+/* Ghost cell `layer` (1 or 2) of wall side `side` (0 -x, 1 +x, 2 -y, 3 +y)
+   at coordinate t along the wall, built from the current state: f~ (16),
+   g~ (9) in the ghost's comoving frame (u_x, u_y, T). */
+int pondref_wall_ghost(const pondref_state* s, int side, int layer, int t, double* f,
+                       double* g, double frame[3]);
 
 /* One quasi-equilibrium half step on a single cell's f (Qf) and g (Qg),
    written in their comoving frame; kappa = (dt/2)(1/tau1 - 1/tau2). */

@@ -20,7 +20,8 @@ class OracleConfig(C.Structure):
                 ("gamma", C.c_double), ("tau", C.c_double), ("prandtl", C.c_double),
                 ("cfl", C.c_double), ("dx", C.c_double), ("bc", C.c_int * 4),
                 ("inflow", (C.c_double * 4) * 4), ("limiter", C.c_int), ("n_corr", C.c_int),
-                ("flat", C.c_int), ("ms_threshold", C.c_double)]
+                ("flat", C.c_int), ("ms_threshold", C.c_double),
+                ("wall", (C.c_double * 3) * 4)]
 
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -58,6 +59,7 @@ def load_library():
     lib.pondref_qe_half_step.argtypes = [C.c_int, C.c_double, _dp, _dp]
     lib.pondref_ms_matrix.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp]
     lib.pondref_get_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.pondref_wall_ghost.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
     _LIB = lib
     return lib
 
@@ -80,6 +82,11 @@ def make_config(wl, transform=TF_LAGRANGE, limiter=LIM_VANLEER, n_corr=0, flat=F
             c.inflow[k][m] = float(wl.inflow[k][m])
     c.limiter, c.n_corr = limiter, n_corr
     c.flat, c.ms_threshold = flat, ms_threshold
+    wall = getattr(wl, "wall", None)
+    if wall is not None:
+        for k in range(4):
+            for m in range(3):
+                c.wall[k][m] = float(wall[k][m])
     return c
 
 
@@ -198,6 +205,13 @@ class Oracle:
         th = np.zeros(n)
         _check(self.lib.pondref_get_lattice(self.h, q.ctypes.data, th.ctypes.data))
         return q.reshape(self.ny, self.nx), th.reshape(self.ny, self.nx)
+
+    def wall_ghost(self, side, layer, t):
+        """(f~, g~, frame) of ghost layer ``layer`` of wall ``side`` at
+        coordinate ``t`` along the wall, from the current state."""
+        f, g, fr = np.zeros(16), np.zeros(9), np.zeros(3)
+        _check(self.lib.pondref_wall_ghost(self.h, side, layer, t, f, g, fr))
+        return f, g, fr
 
     def get_faces(self):
         nx, ny = self.nx, self.ny

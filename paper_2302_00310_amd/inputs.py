@@ -32,6 +32,7 @@ import numpy as np
 BC_PERIODIC = 0
 BC_ZERO_GRADIENT = 1
 BC_INFLOW = 2
+BC_WALL = 3
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -59,6 +60,7 @@ class Workload:
     dx: float = 0.0            # 0 -> 1/nx
     bc: List[int] = field(default_factory=lambda: [BC_PERIODIC] * 4)
     inflow: List[List[float]] = field(default_factory=lambda: [[1.0, 0.0, 0.0, 1.0]] * 4)
+    wall: List[List[float]] = field(default_factory=lambda: [[0.0, 0.0, 1.0]] * 4)  # u_x, u_y, T
     steps: int = 1
     seed: Optional[int] = None
 
@@ -216,6 +218,28 @@ def uniform_2d(nx: int, ny: int, rho: float, ux: float, uy: float, p: float,
                     steps=steps)
 
 
+def thermal_couette_2d(ny: int = 32, nx: int = 4, mach: float = 0.5, eckert: float = 4.0,
+                       prandtl: float = 1.0, tau: float = 10.0, t_cold: float = 1.0,
+                       gamma: float = 1.4, steps: int = 1000) -> Workload:
+    """Thermal Couette flow (Sec. V, viscous flows): walls at y = 0 (at rest,
+    T_C) and y = L = 1 (moving with u_0 = Ma sqrt(gamma T_C) along x, T_H),
+    periodic in x; ny cells across the channel, dx = 1/ny.  The wall
+    temperature difference follows from the Eckert number
+    Ec = u_0^2 / (C_p (T_H - T_C)).  The start is the conduction profile:
+    linear u_x and T, uniform pressure p = T_C."""
+    cp = gamma / (gamma - 1.0)
+    u0 = mach * np.sqrt(gamma * t_cold)
+    t_hot = t_cold + u0 * u0 / (cp * eckert)
+    y = (np.arange(ny) + 0.5) / ny
+    T = np.repeat((t_cold + (t_hot - t_cold) * y)[:, None], nx, axis=1)
+    ux = np.repeat((u0 * y)[:, None], nx, axis=1)
+    p = np.full((ny, nx), t_cold)
+    wall = [[0.0, 0.0, 1.0], [0.0, 0.0, 1.0], [0.0, 0.0, t_cold], [u0, 0.0, t_hot]]
+    return Workload("thermal_couette_2d", 2, nx, ny, p / T, ux, np.zeros((ny, nx)), p,
+                    gamma=gamma, tau=tau, prandtl=prandtl, dx=1.0 / ny,
+                    bc=[BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL], wall=wall, steps=steps)
+
+
 @dataclass
 class Request:
     """One solve of the serving stream."""
@@ -288,5 +312,6 @@ def window(wl: Workload, x0: int, y0: int, wx: int, wy: int) -> Workload:
     w = Workload(wl.name + "_window", wl.dim, len(ix), len(iy), sub(wl.rho), sub(wl.ux),
                  sub(wl.uy), sub(wl.p), gamma=wl.gamma, tau=wl.tau, prandtl=wl.prandtl,
                  cfl=wl.cfl, dx=(wl.dx if wl.dx > 0 else 1.0 / wl.nx), bc=nbc,
-                 inflow=[list(r) for r in wl.inflow], steps=wl.steps, seed=wl.seed)
+                 inflow=[list(r) for r in wl.inflow], wall=[list(r) for r in wl.wall],
+                 steps=wl.steps, seed=wl.seed)
     return w, (int(ix[0]), int(iy[0]))
