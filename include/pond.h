@@ -72,7 +72,17 @@ enum { POND_FP64 = 0, POND_MIXED = 1 };
    interpolation); POND_TF_GRAD is Grad's projection of eq. GradsProjection
    truncated at total order q-1. */
 enum { POND_TF_LAGRANGE = 0, POND_TF_GRAD = 1 };
-enum { POND_BC_PERIODIC = 0, POND_BC_ZERO_GRADIENT = 1, POND_BC_INFLOW = 2 };
+/* Boundary conditions (Sec. IV D).  ZERO_GRADIENT copies the nearest cell;
+   INFLOW imposes the comoving equilibrium of a fixed state.  WALL (2D,
+   POND_D2Q16 only): the two ghost layers mirror the cells next to the wall
+   -- density kept, velocity and temperature reflected about the wall's
+   values -- in their comoving frame, plus the first-order Chapman-Enskog
+   non-equilibrium of the mirrored gradients (central differences of the
+   state at the start of the step).  A ghost off the end of a wall takes
+   the coordinate along the wall the x-then-y ghost rule gives it.  Mass
+   is not exactly conserved through a wall (the ghosts are not exact
+   reflections of the populations). */
+enum { POND_BC_PERIODIC = 0, POND_BC_ZERO_GRADIENT = 1, POND_BC_INFLOW = 2, POND_BC_WALL = 3 };
 enum { POND_LIM_VANLEER = 0, POND_LIM_MINMOD = 1 };
 
 typedef struct {
@@ -90,6 +100,8 @@ typedef struct {
   int limiter;               /* POND_LIM_* (slopes of the MUSCL reconstruction) */
   int n_corr;                /* face-frame corrector passes, 0..4; 0 = the explicit scheme */
   double ms_threshold;       /* POND_D2Q9_D2Q16 switch threshold, >= 0 (0.05 is typical) */
+  double wall[4][3];         /* per side (u_x, u_y, T) of the wall, used where bc = WALL:
+                                T > 0 and no velocity along the wall's normal */
 } pond_config;
 
 typedef struct pond_state pond_state;

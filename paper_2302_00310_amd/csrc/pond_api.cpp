@@ -62,8 +62,17 @@ int validate(const pond_config* c) {
   if (c->n_corr < 0 || c->n_corr > 4) return fail(POND_ERR_INVALID, "n_corr must lie in 0..4");
   const int nside = c->dim == 2 ? 4 : 2;
   for (int k = 0; k < nside; ++k)
-    if (c->bc[k] < POND_BC_PERIODIC || c->bc[k] > POND_BC_INFLOW)
+    if (c->bc[k] < POND_BC_PERIODIC || c->bc[k] > POND_BC_WALL)
       return fail(POND_ERR_INVALID, "unknown boundary condition");
+  for (int k = 0; k < nside; ++k) {
+    if (c->bc[k] != POND_BC_WALL) continue;
+    if (c->dim != 2 || c->lattice != POND_D2Q16)
+      return fail(POND_ERR_UNSUPPORTED, "walls need dim 2 and the D2Q16 f-lattice");
+    const double* w = c->wall[k];
+    if (!(w[2] > 0.0) || !std::isfinite(w[2]) || !std::isfinite(w[0]) || !std::isfinite(w[1]))
+      return fail(POND_ERR_INVALID, "a wall needs a positive temperature and a finite velocity");
+    if (w[k < 2 ? 0 : 1] != 0.0) return fail(POND_ERR_INVALID, "a wall cannot move along its normal");
+  }
   for (int k = 0; k < nside; k += 2)
     if ((c->bc[k] == POND_BC_PERIODIC) != (c->bc[k + 1] == POND_BC_PERIODIC))
       return fail(POND_ERR_INVALID, "a periodic axis needs periodic conditions on both sides");
@@ -96,8 +105,13 @@ Layout layout_of(const pond_config* c) {
   L.ms = c->dim == 2 && (c->lattice == POND_D2Q9 || c->lattice == POND_D2Q9_D2Q16);
   L.lat_bytes = L.ms ? align256(L.cells) : 0;
   L.theta_bytes = L.ms ? align256(L.cells * sizeof(double)) : 0;
+  bool walls = false;
+  for (int k = 0; k < 2 * c->dim; ++k) walls |= c->bc[k] == POND_BC_WALL;
+  // wall ghosts: [side][layer][t] entries, t along the wall (max(nx, ny))
+  L.wall_len = walls ? size_t(std::max(c->nx, c->ny)) : 0;
+  L.wall_bytes = walls ? align256(size_t(8) * L.wall_len * (4 * sizeof(long long) + L.NP * elt)) : 0;
   L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.tab_bytes + L.red_bytes + L.stage_bytes +
-            2 * L.lat_bytes + L.theta_bytes;
+            2 * L.lat_bytes + L.theta_bytes + L.wall_bytes;
   return L;
 }
 
@@ -209,7 +223,11 @@ int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, voi
   if (L.ms) {
     s->lat[0] = reinterpret_cast<unsigned char*>(p); p += L.lat_bytes;
     s->lat[1] = reinterpret_cast<unsigned char*>(p); p += L.lat_bytes;
-    s->theta = reinterpret_cast<double*>(p);
+    s->theta = reinterpret_cast<double*>(p); p += L.theta_bytes;
+  }
+  if (L.wall_bytes) {
+    s->wU = reinterpret_cast<long long*>(p); p += size_t(8) * L.wall_len * 4 * sizeof(long long);
+    s->wN = p;
   }
   s->dx = cfg->dx > 0.0 ? cfg->dx : 1.0 / cfg->nx;
   s->cv = 1.0 / (cfg->gamma - 1.0);
@@ -328,6 +346,18 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   a.inflow = s->inflow_dev;
   a.cells = n;
   a.flag = s->flag;
+  if (s->L.wall_bytes) {
+    a.wU = s->wU;
+    a.wN = s->wN;
+    a.wall_len = int(s->L.wall_len);
+    a.wall_n = 8 * s->L.wall_len;
+    for (int k = 0; k < 4; ++k)
+      for (int q = 0; q < 3; ++q) a.wall[k][q] = c.wall[k][q];
+    a.idx2 = 0.5 / s->dx;
+    a.tau1 = t * s->dt;
+    a.tau2 = t * s->dt / c.prandtl;
+    a.kf = 1.0 + 0.5 / t;
+  }
   return upload_table(s);
 }
 
@@ -341,6 +371,12 @@ int pond_step(pond_state* s, int nsteps) {
         StepArgs a = s->args;
         POND_HIP(launch_switch(a, s->U[s->cur], s->cfg.ms_threshold, s->cfg.gamma, s->theta,
                                s->lat[1 - s->cur], s->stream));
+      }
+      if (s->L.wall_bytes) {
+        // wall ghosts from the state at the start of this step
+        StepArgs a = s->args;
+        a.U_in = s->U[s->cur];
+        POND_HIP(launch_wall_ghosts(s->L.fp64, a, s->stream));
       }
       POND_HIP(launch_step_batch(s->L.fp64, 1u << kind_of(s->cfg.transform, s->args.ms), s->tab, 1,
                                  s->args.tiles_x * s->args.tiles_y, s->cur, s->stream));

@@ -53,6 +53,17 @@ struct StepArgs {
   const unsigned char* lat_in;
   const unsigned char* lat_out;
   int ms;                  // 1: per-cell f-lattices (D2Q9 or multiscale)
+  // walls: ghost layer k (1, 2) of side s at coordinate t along the wall is
+  // entry (2 s + k - 1) wall_len + t of wall_n-long planes, written before
+  // each step by the wall-ghost kernel and read by the tile loader
+  const long long* wU;     // 4 fixed-point ledger planes
+  const void* wN;          // NP non-equilibrium population planes
+  int wall_len;
+  size_t wall_n;
+  double wall[4][3];       // (u_x, u_y, T) of each side's wall
+  double idx2;             // 1 / (2 dx)
+  double tau1, tau2;       // relaxation times (tau2 = tau1 / Pr)
+  double kf;               // 1 + dt / (2 tau1): non-equilibrium scaling of the stored variable
 };
 
 // One solve of a batched step launch: the arguments of its even and odd
@@ -76,6 +87,8 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
 hipError_t launch_switch(const StepArgs& a, const long long* U, double threshold, double gamma,
                          double* theta, unsigned char* lat_out, hipStream_t st);
 hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
+// Wall ghosts of one 2D solve from the ledger a.U_in (into a.wU, a.wN).
+hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, hipStream_t st);
 hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,
                        size_t count, double scale, double cv, void* n, long long* U,
                        hipStream_t st);

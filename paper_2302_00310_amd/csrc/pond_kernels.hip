@@ -28,7 +28,7 @@
 namespace pond {
 namespace {
 
-constexpr int BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1;
+constexpr int BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_WALL = 3;
 constexpr int LIM_VANLEER = 0, LIM_MINMOD = 1;
 constexpr int TF_LAGRANGE = 0, TF_GRAD = 1;
 constexpr double kTieBand = 1e-11;  // |v_n| <= kTieBand sqrt(T_F): upwind tie
@@ -545,8 +545,10 @@ __device__ __forceinline__ constexpr T wg(int i) {
 
 // Conserved moments and non-equilibrium populations of grid cell (gx, gy),
 // which may lie outside the grid: ghost cells follow the boundary rules.
-template <int D, typename T>
-__device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, long long (&U)[4],
+// WALLS = false: the caller never asks for a wall ghost (cells of the grid,
+// or solves on per-cell f-lattices, which take no walls).
+template <int D, typename T, bool WALLS = true>
+__device__ __forceinline__ bool load_cell(const StepArgs& a, int gx, int gy, long long (&U)[4],
                                           T (&n)[Geo<D>::NP]) {
   constexpr int NP = Geo<D>::NP;
   int side = -1;
@@ -556,12 +558,34 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
     sy = gy;
     if (side < 0) sy = resolve(gy, a.ny, a.bc[2], a.bc[3], &side, 2);
   }
+  if constexpr (D == 2 && WALLS) {
+    // (select, not an index: a run-time index into the arguments would put
+    // them in scratch memory)
+    const int bcs = side == 0 ? a.bc[0] : side == 1 ? a.bc[1] : side == 2 ? a.bc[2] : a.bc[3];
+    if (side >= 0 && bcs == BC_WALL) {
+      // wall ghost of layer k at coordinate t along the wall (x first: off
+      // the end of an x wall, y wraps on a periodic axis, else clamps);
+      // slots past the second layer (partial tiles) repeat the second
+      const int v = side < 2 ? gx : gy, nn = side < 2 ? a.nx : a.ny;
+      const int k = min(v < 0 ? -v : v - nn + 1, 2);
+      int t = side < 2 ? gy : sx;
+      if (side < 2 && (t < 0 || t >= a.ny))
+        t = a.bc[2] == BC_PERIODIC ? ((t % a.ny) + a.ny) % a.ny : (t < 0 ? 0 : a.ny - 1);
+      const size_t e = size_t(2 * side + k - 1) * size_t(a.wall_len) + size_t(t);
+      const T* wn = static_cast<const T*>(a.wN);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) U[q] = a.wU[q * a.wall_n + e];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) n[i] = wn[i * a.wall_n + e];
+      return true;
+    }
+  }
   if (side >= 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) U[q] = a.inflow[4 * side + q];
 #pragma unroll
     for (int i = 0; i < NP; ++i) n[i] = T(0);
-    return;
+    return false;
   }
   const T* nin = static_cast<const T*>(a.n_in);
   const size_t cell = size_t(sx) + size_t(a.nx) * size_t(sy);
@@ -569,6 +593,7 @@ __device__ __forceinline__ void load_cell(const StepArgs& a, int gx, int gy, lon
   for (int q = 0; q < 4; ++q) U[q] = a.U_in[q * a.cells + cell];
 #pragma unroll
   for (int i = 0; i < NP; ++i) n[i] = nin[i * a.cells + cell];
+  return false;
 }
 
 // f-lattice of grid cell (gx, gy) for this step (multiscale kernels): the
@@ -1331,7 +1356,7 @@ __device__ __forceinline__ void step_update_ms(const StepArgs& a, int x, int y,
   constexpr int QF = G::QF, QG = G::QG, NP = G::NP;
   long long U[4];
   T own[NP];
-  load_cell<2, T>(a, x, y, U, own);
+  load_cell<2, T, false>(a, x, y, U, own);
   int q, qo;
   cell_lattice(a, x, y, &q, &qo);
   relattice(own, qo, q);
@@ -1518,7 +1543,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
   if (own_in) {
     long long U[4];
     T own[NP];
-    load_cell<D, T>(a, x0 + cx, y0 + cy, U, own);
+    load_cell<D, T, false>(a, x0 + cx, y0 + cy, U, own);
     const Frame f0 = gauge(U, a);  // the frame the populations are written in
     qe_half<D, T>(own, own + QF, kappa);
     const T b = T(a.b_upd), lam = T(a.lam);
@@ -1581,7 +1606,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     const int gx = x0 + hx - 2, gy = y0 + hy - G::OY;
     long long U[4];
     T n[NP];
-    load_cell<D, T>(a, gx, gy, U, n);
+    // a wall ghost is built at the start of the step with its relaxed
+    // non-equilibrium: the first QE half step does not act on it
+    const bool wall = load_cell<D, T, MS == 0>(a, gx, gy, U, n);
+    const T kap = wall ? T(0) : kappa;
     const Frame fr = gauge(U, a);
     const int h = hx + G::HX * hy;
     const T r = T(fr.rho), rg = T(a.geq * fr.T * fr.rho);
@@ -1592,7 +1620,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
       cell_lattice(a, gx, gy, &qn, &qo);
       relattice(n, qo, qn);
       sm.Lat[h] = (unsigned char)qn;
-      qe_half<D, T>(n, n + QF, kappa, qn == 4);
+      qe_half<D, T>(n, n + QF, kap, qn == 4);
       if (qn == 4) {
 #pragma unroll
         for (int i = 0; i < QF; ++i) sm.P[i * G::NH + h] = r * wf<D, T>(i) + apre * n[i];
@@ -1601,7 +1629,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
         for (int i = 0; i < 9; ++i) sm.P[i * G::NH + h] = r * wg<D, T>(i) + apre * n[i];
       }
     } else {
-      qe_half<D, T>(n, n + QF, kappa);
+      qe_half<D, T>(n, n + QF, kap);
 #pragma unroll
       for (int i = 0; i < QF; ++i) sm.P[i * G::NH + h] = r * wf<D, T>(i) + apre * n[i];
     }
@@ -1737,6 +1765,110 @@ __global__ void switch_lattice_kernel(StepArgs a, const double* theta, double th
 }
 
 // --------------------------------------------------------------------------
+// Wall ghosts (Sec. IV D).  Ghost layer k of a wall mirrors the k-th cell in
+// from the wall: same density, velocity and temperature reflected about the
+// wall's values.  Its populations are the comoving equilibrium plus the
+// first-order Chapman-Enskog non-equilibrium, expanded on Hermite
+// polynomials of c = (v - u_G) / sqrt(T_G) (order 3 on D2Q16 for f, order
+// 2 on D2Q9 for g), from the gradients of the mirror-extended field by
+// central differences (along the wall, past the grid, a periodic axis wraps
+// and the others take the nearest cell).  With p = rho T, S = grad u +
+// (grad u)^T, d = div u and c_e = C_v - 1:
+//   f: second moments -tau1 p (S - (d / C_v) I), third central moments
+//      -tau2 p [dT/dx_a delta_bc]_cyc;
+//   g: zeroth moment tau1 c_e p d / C_v, first central -tau2 c_e p grad T,
+//      second central -tau1 c_e p T (S - (2 d / C_v) I),
+// so the non-equilibrium carries no mass, momentum or energy.  Stored as
+// n = (1 + dt / (2 tau1)) f^neq with the ghost's ledger moments.
+// --------------------------------------------------------------------------
+struct Prim {
+  double rho, ux, uy, T;
+};
+
+// Extended field next to wall `side`: m >= 0 the interior cell m rows in,
+// m < 0 ghost layer -m.
+__device__ __forceinline__ Prim wall_field(const StepArgs& a, int side, int m, int t) {
+  const int nt = side < 2 ? a.ny : a.nx;
+  const int bt = side < 2 ? a.bc[2] : a.bc[0];
+  if (t < 0 || t >= nt) t = bt == BC_PERIODIC ? ((t % nt) + nt) % nt : (t < 0 ? 0 : nt - 1);
+  const int mm = m >= 0 ? m : -m - 1;
+  const int x = side == 0 ? mm : side == 1 ? a.nx - 1 - mm : t;
+  const int y = side == 2 ? mm : side == 3 ? a.ny - 1 - mm : t;
+  const size_t cell = size_t(x) + size_t(a.nx) * size_t(y);
+  long long u[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) u[q] = a.U_in[q * a.cells + cell];
+  const Frame f = gauge(u, a);
+  Prim p{f.rho, f.ux, f.uy, f.T};
+  if (m < 0) {
+    p.ux = 2.0 * a.wall[side][0] - p.ux;
+    p.uy = 2.0 * a.wall[side][1] - p.uy;
+    p.T = 2.0 * a.wall[side][2] - p.T;
+  }
+  return p;
+}
+
+template <typename T>
+__global__ void wall_ghost_kernel(StepArgs a) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= a.wall_n) return;
+  const int L = a.wall_len;
+  const int side = int(e / size_t(2 * L)), k = int((e / size_t(L)) % 2) + 1, t = int(e % size_t(L));
+  if (a.bc[side] != BC_WALL || t >= (side < 2 ? a.ny : a.nx)) return;
+  const Prim g = wall_field(a, side, -k, t);
+  const Prim in = wall_field(a, side, -k + 1, t), out = wall_field(a, side, -k - 1, t);
+  const Prim tp = wall_field(a, side, -k, t + 1), tm = wall_field(a, side, -k, t - 1);
+  // derivatives along the inward normal and along the wall
+  const double sn = (side == 0 || side == 2) ? a.idx2 : -a.idx2;
+  const double nux = sn * (in.ux - out.ux), nuy = sn * (in.uy - out.uy), nT = sn * (in.T - out.T);
+  const double tux = a.idx2 * (tp.ux - tm.ux), tuy = a.idx2 * (tp.uy - tm.uy), tT = a.idx2 * (tp.T - tm.T);
+  const bool xw = side < 2;
+  const double dxux = xw ? nux : tux, dxuy = xw ? nuy : tuy, dxT = xw ? nT : tT;
+  const double dyux = xw ? tux : nux, dyuy = xw ? tuy : nuy, dyT = xw ? tT : nT;
+  const double p = g.rho * g.T, icv = a.icv, ce = a.cv - 1.0;
+  const double d = dxux + dyuy;
+  const double sxx = 2.0 * dxux, syy = 2.0 * dyuy, sxy = dxuy + dyux;
+  const double iT = 1.0 / g.T, irt = sqrt(iT), i32 = iT * irt;
+  // f Hermite coefficients (a, b) = (x order, y order)
+  const double v = -a.tau1 * p * iT;
+  const double f20 = v * (sxx - d * icv), f02 = v * (syy - d * icv), f11 = v * sxy;
+  const double w = -a.tau2 * p * i32;
+  const double f30 = 3.0 * w * dxT, f21 = w * dyT, f12 = w * dxT, f03 = 3.0 * w * dyT;
+  // g Hermite coefficients
+  const double g00 = a.tau1 * ce * p * d * icv;
+  const double g10 = -a.tau2 * ce * p * dxT * irt, g01 = -a.tau2 * ce * p * dyT * irt;
+  const double u2 = -a.tau1 * ce * p;
+  const double g20 = u2 * (sxx - 2.0 * d * icv) - g00, g02 = u2 * (syy - 2.0 * d * icv) - g00;
+  const double g11 = u2 * sxy;
+  T* wn = static_cast<T*>(const_cast<void*>(a.wN));
+  long long* wu = const_cast<long long*>(a.wU);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const double cx = node<4, double>(i & 3), cy = node<4, double>(i >> 2);
+    const double hx2 = cx * cx - 1.0, hy2 = cy * cy - 1.0;
+    const double hx3 = cx * (cx * cx - 3.0), hy3 = cy * (cy * cy - 3.0);
+    const double s2 = 0.5 * (f20 * hx2 + f02 * hy2) + f11 * cx * cy;
+    const double s3 = (f30 * hx3 + f03 * hy3) * (1.0 / 6.0) + 0.5 * (f21 * hx2 * cy + f12 * cx * hy2);
+    wn[i * a.wall_n + e] = T(a.kf * weight<4, double>(i & 3) * weight<4, double>(i >> 2) * (s2 + s3));
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double cx = node<3, double>(i % 3), cy = node<3, double>(i / 3);
+    const double s = g00 + g10 * cx + g01 * cy + 0.5 * (g20 * (cx * cx - 1.0) + g02 * (cy * cy - 1.0)) +
+                     g11 * cx * cy;
+    wn[(16 + i) * a.wall_n + e] = T(a.kf * weight<3, double>(i % 3) * weight<3, double>(i / 3) * s);
+  }
+  int bad = 0;
+  wu[e] = to_fixed(g.rho, a.scale, &bad);
+  wu[a.wall_n + e] = to_fixed(g.rho * g.ux, a.scale, &bad);
+  wu[2 * a.wall_n + e] = to_fixed(g.rho * g.uy, a.scale, &bad);
+  wu[3 * a.wall_n + e] =
+      to_fixed(a.cv * p + 0.5 * g.rho * (g.ux * g.ux + g.uy * g.uy), a.scale, &bad);
+  raise_flag(a.flag, !(g.rho > 0.0) || !(g.T > 0.0), 1);
+  raise_flag(a.flag, bad != 0, 2);
+}
+
+// --------------------------------------------------------------------------
 // Initial data, observables, exact totals.
 // --------------------------------------------------------------------------
 template <int D, typename T>
@@ -1845,6 +1977,13 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
     if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 1>), grid, block, 0, st, tab, n, parity);
     else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 1>), grid, block, 0, st, tab, n, parity);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, hipStream_t st) {
+  const dim3 grid(unsigned((a.wall_n + 255) / 256)), block(256);
+  if (fp64) hipLaunchKernelGGL(wall_ghost_kernel<double>, grid, block, 0, st, a);
+  else hipLaunchKernelGGL(wall_ghost_kernel<float>, grid, block, 0, st, a);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ struct Layout {
   int red_blocks = 256;
   bool ms = false;                 // per-cell f-lattices (D2Q9 or multiscale)
   size_t lat_bytes = 0, theta_bytes = 0;
+  size_t wall_len = 0, wall_bytes = 0;  // wall ghost entries per side and layer; their bytes
   size_t total = 0;
 };
 
@@ -47,6 +48,8 @@ struct pond_state {
   double* stage = nullptr;
   unsigned char* lat[2] = {nullptr, nullptr};  // f-lattice per cell of n[0], n[1]
   double* theta = nullptr;                     // multiscale switch indicator
+  long long* wU = nullptr;                     // wall ghosts: 4 ledger planes of 8 wall_len entries
+  void* wN = nullptr;                          // wall ghosts: NP population planes
   int cur = 0;
   int64_t nstep = 0;
   bool initialized = false;

@@ -21,7 +21,7 @@ ERRORS = {-1: "POND_ERR_INVALID", -2: "POND_ERR_NOMEM", -3: "POND_ERR_DEVICE",
 POND_D1Q4, POND_D2Q16, POND_D2Q9, POND_D2Q9_D2Q16 = 1, 2, 3, 4
 POND_FP64, POND_MIXED = 0, 1
 POND_TF_LAGRANGE, POND_TF_GRAD = 0, 1
-POND_BC_PERIODIC, POND_BC_ZERO_GRADIENT, POND_BC_INFLOW = 0, 1, 2
+POND_BC_PERIODIC, POND_BC_ZERO_GRADIENT, POND_BC_INFLOW, POND_BC_WALL = 0, 1, 2, 3
 POND_LIM_VANLEER, POND_LIM_MINMOD = 0, 1
 
 
@@ -36,7 +36,8 @@ class pond_config(C.Structure):
                 ("transform", C.c_int), ("precision", C.c_int), ("gamma", C.c_double),
                 ("tau", C.c_double), ("prandtl", C.c_double), ("cfl", C.c_double),
                 ("dx", C.c_double), ("bc", C.c_int * 4), ("inflow", (C.c_double * 4) * 4),
-                ("limiter", C.c_int), ("n_corr", C.c_int), ("ms_threshold", C.c_double)]
+                ("limiter", C.c_int), ("n_corr", C.c_int), ("ms_threshold", C.c_double),
+                ("wall", (C.c_double * 3) * 4)]
 
 
 _dbl = C.POINTER(C.c_double)
@@ -222,6 +223,11 @@ def make_config(wl, precision=POND_FP64, transform=POND_TF_LAGRANGE, limiter=PON
         c.bc[k] = int(wl.bc[k])
         for m in range(4):
             c.inflow[k][m] = float(wl.inflow[k][m])
+    wall = getattr(wl, "wall", None)
+    if wall is not None:
+        for k in range(4):
+            for m in range(3):
+                c.wall[k][m] = float(wall[k][m])
     c.limiter, c.n_corr = limiter, n_corr
     return c
 

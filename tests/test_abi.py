@@ -115,3 +115,28 @@ def test_f_lattice_rules(pond):
     ms = pond.pond_state_bytes(_cfg(pond, lattice=4, transform=1))
     assert ms >= base + 32 * 32 * (2 + 8)
     assert pond.pond_state_bytes(_cfg(pond, lattice=3, transform=1)) == ms
+
+
+def test_wall_config_rules(pond):
+    """Walls: 2D and the D2Q16 f-lattice only (else unsupported), a positive
+    wall temperature and no wall velocity along the normal; the footprint
+    adds the ghost buffers (8 layers of max(nx, ny) entries)."""
+    wl = inputs.thermal_couette_2d(ny=32, nx=40)
+    ok = pond.make_config(wl)
+    base = pond.pond_state_bytes(pond.make_config(
+        inputs.Workload("q", 2, 40, 32, wl.rho, wl.ux, wl.uy, wl.p, dx=wl.dx)))
+    size = pond.pond_state_bytes(ok)
+    assert size >= base + 8 * 40 * (4 * 8 + 25 * 4)
+    bad = pond.make_config(wl, transform=1, lattice=pond.POND_D2Q9)
+    assert pond.pond_state_bytes(bad) == 0
+    h = C.c_void_p()
+    assert pond.load_library().pond_create(C.byref(bad), None, 0, None, C.byref(h)) == -6
+    c = pond.make_config(wl)
+    c.wall[3][1] = 0.1                  # top wall moving along y: its normal
+    assert pond.pond_state_bytes(c) == 0
+    c = pond.make_config(wl)
+    c.wall[2][2] = 0.0
+    assert pond.pond_state_bytes(c) == 0
+    c = pond.make_config(wl)
+    c.bc[2] = 4
+    assert pond.pond_state_bytes(c) == 0

@@ -1,0 +1,152 @@
+"""Parity of the GPU step with the FP64 oracle on walls (Sec. IV D: mirrored
+ghost cells with the Chapman-Enskog non-equilibrium of the mirrored
+gradients), on walls along y, along x, on all four sides and next to inflow
+and zero-gradient sides, with both frame transformations and Pr < 1.
+
+FP64: moments within 1e-12 of the oracle; mixed precision: within 1e-5
+relative L2; the full 2048^2 box on sampled cells against oracle windows
+that hold each cell's domain of dependence (three cells per step: the
+two-cell stencil and the ghosts' gradients one cell along the wall)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_00310_amd import inputs
+from paper_2302_00310_amd.inputs import (BC_INFLOW, BC_PERIODIC, BC_WALL, BC_ZERO_GRADIENT,
+                                         Workload)
+
+from .gpu_common import moment_errors, rel_err, window_samples
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = 0, 1
+LAGRANGE, GRAD = 0, 1
+
+
+@pytest.fixture(scope="module")
+def pond():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2302_00310_amd import pond as p
+    p.load_library()
+    return p
+
+
+def with_walls(wl, bc, wall, prandtl=0.7):
+    return Workload(wl.name + "_walls", 2, wl.nx, wl.ny, wl.rho, wl.ux, wl.uy, wl.p, gamma=wl.gamma,
+                    tau=wl.tau, prandtl=prandtl, dx=wl.dx if wl.dx > 0 else 1.0 / wl.nx, bc=bc,
+                    inflow=[list(r) for r in wl.inflow], wall=wall, steps=wl.steps)
+
+
+def transposed(wl):
+    t = lambda a: np.ascontiguousarray(a.T)
+    b = wl.bc
+    w = wl.wall
+    return Workload(wl.name + "_T", 2, wl.ny, wl.nx, t(wl.rho), t(wl.uy), t(wl.ux), t(wl.p),
+                    gamma=wl.gamma, tau=wl.tau, prandtl=wl.prandtl, dx=wl.dx,
+                    bc=[b[2], b[3], b[0], b[1]],
+                    wall=[[w[2][1], w[2][0], w[2][2]], [w[3][1], w[3][0], w[3][2]],
+                          [w[0][1], w[0][0], w[0][2]], [w[1][1], w[1][0], w[1][2]]])
+
+
+def couette():
+    return inputs.thermal_couette_2d(ny=33, nx=37, prandtl=0.7, eckert=4.0, tau=3.0)
+
+
+def cavity(n=35, ny=34, lid=0.4):
+    v = inputs.vortex_2d(n, steps=1, noise=1e-3, ny=ny, mach=0.5)
+    return with_walls(v, [BC_WALL] * 4, [[0, 0, 1.0], [0, 0, 1.0], [0, 0, 1.0], [lid, 0, 1.1]])
+
+
+def channel():
+    s = inputs.shu_osher_2d(40, 20, steps=1)
+    return with_walls(s, [BC_INFLOW, BC_ZERO_GRADIENT, BC_WALL, BC_WALL],
+                      [[0, 0, 1], [0, 0, 1], [0, 0, 1.5], [0.2, 0, 1.5]])
+
+
+CASES = {
+    "couette_37x33": couette,
+    "couette_x_33x37": lambda: transposed(couette()),
+    "cavity_35x34": cavity,
+    "channel_inflow_40x20": channel,
+}
+
+
+@pytest.mark.parametrize("transform", [LAGRANGE, GRAD])
+@pytest.mark.parametrize("name", list(CASES))
+def test_walls_fp64_match_oracle(pond, name, transform):
+    wl = CASES[name]()
+    print("walls fp64", name, transform, flush=True)
+    s = pond.Solver(wl, precision=FP64, transform=transform)
+    o = oracle.Oracle(wl, transform=transform)
+    assert s.dt == pytest.approx(o.dt, rel=1e-14)
+    try:
+        for _ in range(3):
+            s.step(8)
+            o.step(8)
+            e = moment_errors(s.moments(), o.moments())
+            assert max(e.values()) <= 1e-12, e
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("name", ["couette_37x33", "cavity_35x34", "channel_inflow_40x20"])
+def test_walls_mixed_match_oracle(pond, name):
+    wl = CASES[name]()
+    s = pond.Solver(wl, precision=MIXED)
+    o = oracle.Oracle(wl)
+    try:
+        s.step(40)
+        o.step(40)
+        e = moment_errors(s.moments(), o.moments(), l2=True)
+        assert max(e.values()) <= 1e-5, e
+    finally:
+        s.close()
+
+
+def test_thermal_couette_reaches_the_closed_form_on_the_gpu(pond):
+    """The mixed GPU step on the 16-cell thermal Couette flow at Pr = 0.5
+    meets the closed-form profile as the oracle does (within 2.5% of
+    T_H - T_C) and stays within 1e-5 of the oracle's steady profile."""
+    pr, ec = 0.5, 4.0
+    wl = inputs.thermal_couette_2d(ny=16, prandtl=pr, eckert=ec, tau=10.0)
+    s = pond.Solver(wl, precision=MIXED)
+    o = oracle.Oracle(wl)
+    steps = int(0.75 / (wl.tau * o.dt * o.dt))
+    try:
+        s.step(steps)
+        T = s.moments()[3]
+    finally:
+        s.close()
+    o.step(steps)
+    To = o.moments()[3]
+    y = (np.arange(16) + 0.5) / 16
+    tc, th = wl.wall[2][2], wl.wall[3][2]
+    want = tc + (th - tc) * (y + pr * ec / 2 * y * (1 - y))
+    assert np.abs(T[:, 0] - want).max() / (th - tc) < 0.025
+    assert rel_err(T, To) <= 1e-5
+
+
+def test_walls_full_size_sampled_cells(pond):
+    """A 2048^2 box with walls on all four sides (moving lid) and the
+    vortex field, mixed precision, 4 steps: sampled cells at the corners,
+    along the walls and inside against oracle windows."""
+    v = inputs.vortex_2d(2048, steps=4, noise=1e-3, mach=0.5)
+    wl = with_walls(v, [BC_WALL] * 4, [[0, 0, 1.0], [0, 0, 1.0], [0, 0, 1.0], [0.3, 0, 1.1]])
+    steps = 4
+    n = wl.nx
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (1, 700), (n - 2, 1300), (900, 1),
+           (1500, n - 2), (n // 2, n // 2), (40, 2)]
+    for precision in (FP64, MIXED):
+        print("walls full size", precision, flush=True)
+        ref, dt = window_samples(wl, pts, steps, dep=3)
+        s = pond.Solver(wl, precision=precision)
+        try:
+            assert abs(s.dt / dt - 1.0) < 1e-15
+            s.step(steps)
+            m = s.moments()
+        finally:
+            s.close()
+        got = np.array([[float(a[y, x]) for a in m] for (x, y) in pts])
+        e = moment_errors(tuple(got.T), tuple(ref.T), l2=(precision == MIXED))
+        assert max(e.values()) <= (1e-12 if precision == FP64 else 1e-5), (precision, e)
