@@ -38,10 +38,10 @@ BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
 KERNEL_SOURCES = ("paper_2302_00310_amd/csrc/pond_kernels.hip",
                   "paper_2302_00310_amd/csrc/pond_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "048528c8d2023e1d597116e013dee77683af8552868d03c68229e301e4548482",
+    "sha256": "d08e7fec9ff846e5dbca30dcb93e228f197961c7a20a3da40b1956e91df96b0a",
     "n": 2048,
-    "fetch_bytes": 1.64724e+09,
-    "write_bytes": 7.89575e+08,
+    "fetch_bytes": 1.65231e+09,
+    "write_bytes": 7.88966e+08,
 }
 
 
@@ -94,6 +94,7 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-multiscale", action="store_true",
                    help="skip the multiscale D2Q9/D2Q16 leg")
+    p.add_argument("--no-walls", action="store_true", help="skip the wall-boundary leg")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--serving-requests", type=int, default=64,
                    help="requests of the serving leg (0 skips it)")
@@ -238,6 +239,36 @@ def serving_leg(n_req, sizes, arena_gb, max_active):
             "server": stats}
 
 
+def walls_leg(n, steps, warmup):
+    """Wall boundaries (mirrored Chapman-Enskog ghost cells, one ghost kernel
+    per step before the step kernel), mixed precision, Lagrange maps: the
+    thermal Couette channel n^2 (walls along y, periodic x) and a closed box
+    n^2 (walls on all sides, moving lid, the advected-vortex field), each
+    against the same fields on a periodic grid."""
+    from paper_2302_00310_amd import inputs, pond
+    from paper_2302_00310_amd.inputs import BC_PERIODIC, BC_WALL, Workload
+    cells = n * n
+    cou = inputs.thermal_couette_2d(ny=n, nx=n, prandtl=0.71, eckert=4.0)
+    v = inputs.vortex_2d(n, steps=1, mach=0.5)
+    box = Workload("walled_box", 2, n, n, v.rho, v.ux, v.uy, v.p, tau=v.tau, prandtl=v.prandtl,
+                   dx=1.0 / n, bc=[BC_WALL] * 4,
+                   wall=[[0, 0, 1.0], [0, 0, 1.0], [0, 0, 1.0], [0.3, 0, 1.1]])
+    res = {}
+    for key, wl, desc in (
+            ("thermal_couette", cou, f"thermal Couette channel {n}x{n}, Ma 0.5, Ec 4, Pr 0.71"),
+            ("walled_box", box, f"closed box {n}x{n}, lid 0.3, isentropic vortex at Mach 0.5")):
+        per = Workload(wl.name + "_periodic", 2, n, n, wl.rho, wl.ux, wl.uy, wl.p, tau=wl.tau,
+                       prandtl=wl.prandtl, dx=wl.dx, bc=[BC_PERIODIC] * 4)
+        out = {"workload": desc + "; mixed precision"}
+        for name, w in (("walls", wl), ("periodic", per)):
+            wall, kern = time_path(w, pond.POND_MIXED, steps, warmup)
+            out[name] = {"value": cells * steps / wall, "unit": "cell-updates/s",
+                         "ms_per_step": kern}
+        out["walls_over_periodic"] = out["walls"]["value"] / out["periodic"]["value"]
+        res[key] = out
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -281,6 +312,8 @@ def main():
         out["mixed_over_fp64"] = value / v64
     if not a.no_multiscale:
         out["multiscale"] = multiscale_leg(max(1, a.steps // 2), a.warmup)
+    if not a.no_walls:
+        out["walls"] = walls_leg(a.n, max(1, a.steps // 2), a.warmup)
     if a.serving_requests > 0:
         sizes = tuple(int(v) for v in a.serving_sizes.split(","))
         out["serving"] = serving_leg(a.serving_requests, sizes, a.serving_arena_gb,
