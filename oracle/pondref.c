@@ -427,6 +427,9 @@ static int check_config(const pondref_config* c) {
       return fail("a wall needs a positive temperature and a finite velocity");
     if (c->wall[k][k < 2 ? 0 : 1] != 0.0) return fail("a wall cannot move along its normal");
   }
+  if (!isfinite(c->accel[0]) || !isfinite(c->accel[1])) return fail("the body force must be finite");
+  if ((c->accel[0] != 0.0 || c->accel[1] != 0.0) && (c->dim != 2 || c->flat != PONDREF_F_D2Q16))
+    return fail("a body force needs 2D and the D2Q16 f-lattice");
   for (int a = 0; a < nside; a += 2)
     if ((c->bc[a] == PONDREF_BC_PERIODIC) != (c->bc[a + 1] == PONDREF_BC_PERIODIC))
       return fail("a periodic axis needs periodic conditions on both sides");
@@ -1064,12 +1067,53 @@ static void face_flux(const pondref_state* s, const face_stencil* st, double* fo
 }
 
 /* ------------------------------------------------------------------------ */
+/* Body force (App. D): Strang half step of d f_i / dt = F_i with           */
+/* F_i = a . (v_i - u) / T f^eq_i, one explicit Euler step of dt / 2:        */
+/* f* = f + (dt/2) F, which moves the velocity to u* = u + (dt/2) a.          */
+/* reading: the printed F carries a minus sign that would decelerate the     */
+/* flow while u* accelerates it; the sign is taken so that the force adds    */
+/* (dt/2) rho a of momentum, as u* states.  In the comoving frame            */
+/* (v - u)/T = c / sqrt(T) and f^eq = rho W.  Applied to the stored f~ (its  */
+/* moments are those of f); g is not forced.  The cell then takes the       */
+/* comoving frame of its new moments (u*, and T from the energy, which the   */
+/* Euler step changes by (dt/2) rho a.u), re-gauged as after the update.    */
+/* ------------------------------------------------------------------------ */
+static void force_half_step(pondref_state* s, int c) {
+  double* f = s->f + (size_t)c * s->Qf;
+  double* g = s->g + (size_t)c * s->Qg;
+  double* fr = s->fr + 3 * c;
+  const double ax = s->cfg.accel[0], ay = s->cfg.accel[1];
+  double rho = 0.0;
+  for (int i = 0; i < 16; i++) rho += f[i];
+  const double rt = sqrt(fr[2]);
+  for (int i = 0; i < 16; i++)
+    f[i] += 0.5 * s->dt * rho * s->Wf[i] * (ax * s->cfx[i] + ay * s->cfy[i]) / rt;
+  double r2, ux, uy, T, Gg[81], tf[QMAX], tg[9];
+  moments(s, 4, f, g, fr, &r2, &ux, &uy, &T, NULL);
+  const double nfr[3] = {ux, uy, T};
+  xf_f(s, 4, fr, 4, nfr, f, tf);
+  transform_matrix(2, &s->Lg, s->cfg.transform, fr, nfr, Gg);
+  matvec(9, Gg, g, tg);
+  memcpy(f, tf, sizeof(double) * 16);
+  memcpy(g, tg, sizeof(double) * 9);
+  memcpy(fr, nfr, sizeof nfr);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One time step t_n -> t_{n+1}.                                             */
 /* ------------------------------------------------------------------------ */
 static void one_step(pondref_state* s) {
   const int nx = s->cfg.nx, ny = s->cfg.ny, D = s->D, Qf = s->Qf, Qg = s->Qg;
   const int twod = D == 2;
   const double tau = s->tau1, dt = s->dt, lam = dt / s->dx;
+
+  const int forced = s->cfg.accel[0] != 0.0 || s->cfg.accel[1] != 0.0;
+  /* body force, first half step (App. D) */
+  if (forced) {
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; y++)
+      for (int x = 0; x < nx; x++) force_half_step(s, cidx(s, x, y));
+  }
 
   /* multiscale: choose each cell's f-lattice for this step (Sec. IV C) */
   if (twod && s->cfg.flat == PONDREF_F_MULTISCALE) {
@@ -1206,6 +1250,8 @@ static void one_step(pondref_state* s) {
       memcpy(fr, nfr, sizeof nfr);
       /* second quasi-equilibrium half step */
       qe_half_step(s, qc, f, g);
+      /* body force, second half step */
+      if (forced) force_half_step(s, c);
     }
   s->nstep++;
 }

@@ -53,6 +53,8 @@ typedef struct {
                                cells), D2Q9 elsewhere */
   double wall[4][3];        /* u_x, u_y, T of the wall per side (used if WALL;
                                T > 0, no velocity normal to the wall) */
+  double accel[2];          /* body-force acceleration a (App. D; 2D, D2Q16);
+                               0 = no force */
 } pondref_config;
 
 typedef struct pondref_state pondref_state;

@@ -21,7 +21,7 @@ class OracleConfig(C.Structure):
                 ("cfl", C.c_double), ("dx", C.c_double), ("bc", C.c_int * 4),
                 ("inflow", (C.c_double * 4) * 4), ("limiter", C.c_int), ("n_corr", C.c_int),
                 ("flat", C.c_int), ("ms_threshold", C.c_double),
-                ("wall", (C.c_double * 3) * 4)]
+                ("wall", (C.c_double * 3) * 4), ("accel", C.c_double * 2)]
 
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -87,6 +87,9 @@ def make_config(wl, transform=TF_LAGRANGE, limiter=LIM_VANLEER, n_corr=0, flat=F
         for k in range(4):
             for m in range(3):
                 c.wall[k][m] = float(wall[k][m])
+    accel = getattr(wl, "accel", None)
+    if accel is not None:
+        c.accel[0], c.accel[1] = float(accel[0]), float(accel[1])
     return c
 
 

@@ -61,6 +61,7 @@ class Workload:
     bc: List[int] = field(default_factory=lambda: [BC_PERIODIC] * 4)
     inflow: List[List[float]] = field(default_factory=lambda: [[1.0, 0.0, 0.0, 1.0]] * 4)
     wall: List[List[float]] = field(default_factory=lambda: [[0.0, 0.0, 1.0]] * 4)  # u_x, u_y, T
+    accel: List[float] = field(default_factory=lambda: [0.0, 0.0])  # body-force acceleration
     steps: int = 1
     seed: Optional[int] = None
 
@@ -240,6 +241,24 @@ def thermal_couette_2d(ny: int = 32, nx: int = 4, mach: float = 0.5, eckert: flo
                     bc=[BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL], wall=wall, steps=steps)
 
 
+def poiseuille_2d(ny: int = 32, nx: int = 4, u_max: float = 0.05, reynolds: float = 10.0,
+                  t_wall: float = 1.0, gamma: float = 1.4, steps: int = 1000) -> Workload:
+    """Force-driven channel flow (Sec. V, viscous flows): walls at rest at
+    y = 0 and y = L = 1 at temperature t_wall, periodic in x, ny cells across,
+    dx = 1/ny, fluid at rest with rho = 1, T = t_wall.  The acceleration
+    a = 8 nu u_max / L^2 along x, with nu = u_max L / Re, gives the centre
+    speed u_max of the steady Navier-Stokes profile; ``tau`` (tau1 / dt) is
+    left at 1 and set by the caller from nu and dt (nu = tau1 T)."""
+    one = np.ones((ny, nx))
+    nu = u_max / reynolds
+    a = 8.0 * nu * u_max
+    return Workload("poiseuille_2d", 2, nx, ny, one.copy(), 0.0 * one, 0.0 * one, t_wall * one,
+                    gamma=gamma, tau=1.0, prandtl=1.0, dx=1.0 / ny,
+                    bc=[BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL],
+                    wall=[[0.0, 0.0, 1.0], [0.0, 0.0, 1.0], [0.0, 0.0, t_wall], [0.0, 0.0, t_wall]],
+                    accel=[a, 0.0], steps=steps)
+
+
 @dataclass
 class Request:
     """One solve of the serving stream."""
@@ -313,5 +332,5 @@ def window(wl: Workload, x0: int, y0: int, wx: int, wy: int) -> Workload:
                  sub(wl.uy), sub(wl.p), gamma=wl.gamma, tau=wl.tau, prandtl=wl.prandtl,
                  cfl=wl.cfl, dx=(wl.dx if wl.dx > 0 else 1.0 / wl.nx), bc=nbc,
                  inflow=[list(r) for r in wl.inflow], wall=[list(r) for r in wl.wall],
-                 steps=wl.steps, seed=wl.seed)
+                 accel=list(wl.accel), steps=wl.steps, seed=wl.seed)
     return w, (int(ix[0]), int(iy[0]))
