@@ -95,6 +95,7 @@ def parse():
     p.add_argument("--no-multiscale", action="store_true",
                    help="skip the multiscale D2Q9/D2Q16 leg")
     p.add_argument("--no-walls", action="store_true", help="skip the wall-boundary leg")
+    p.add_argument("--no-force", action="store_true", help="skip the body-force leg")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--serving-requests", type=int, default=64,
                    help="requests of the serving leg (0 skips it)")
@@ -269,6 +270,28 @@ def walls_leg(n, steps, warmup):
     return res
 
 
+def force_leg(n, steps, warmup):
+    """Body force (two Strang half steps per step, each an Euler update and a
+    re-gauge, fused into the step kernel), mixed precision, Lagrange maps:
+    the advected vortex n^2 with and without a constant acceleration, and the
+    force-driven channel n^2 between walls (Re 2)."""
+    from paper_2302_00310_amd import inputs, pond
+    from paper_2302_00310_amd.inputs import Workload
+    cells = n * n
+    v = inputs.vortex_2d(n, steps=1)
+    acc = Workload("vortex_forced", 2, n, n, v.rho, v.ux, v.uy, v.p, tau=v.tau, prandtl=v.prandtl,
+                   dx=v.dx, bc=list(v.bc), accel=[0.5, -0.3])
+    ch = inputs.poiseuille_2d(ny=n, nx=n, u_max=0.05, reynolds=2.0)
+    ch.tau = 0.55
+    out = {"workload": f"isentropic vortex {n}^2 at Mach 2 (seed 2) with a = (0.5, -0.3); "
+                       f"force-driven channel {n}x{n} between walls; mixed precision"}
+    for name, w in (("vortex_forced", acc), ("vortex_unforced", v), ("channel", ch)):
+        wall, kern = time_path(w, pond.POND_MIXED, steps, warmup)
+        out[name] = {"value": cells * steps / wall, "unit": "cell-updates/s", "ms_per_step": kern}
+    out["forced_over_unforced"] = out["vortex_forced"]["value"] / out["vortex_unforced"]["value"]
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -314,6 +337,8 @@ def main():
         out["multiscale"] = multiscale_leg(max(1, a.steps // 2), a.warmup)
     if not a.no_walls:
         out["walls"] = walls_leg(a.n, max(1, a.steps // 2), a.warmup)
+    if not a.no_force:
+        out["force"] = force_leg(a.n, max(1, a.steps // 2), a.warmup)
     if a.serving_requests > 0:
         sizes = tuple(int(v) for v in a.serving_sizes.split(","))
         out["serving"] = serving_leg(a.serving_requests, sizes, a.serving_arena_gb,

@@ -102,6 +102,11 @@ typedef struct {
   double ms_threshold;       /* POND_D2Q9_D2Q16 switch threshold, >= 0 (0.05 is typical) */
   double wall[4][3];         /* per side (u_x, u_y, T) of the wall, used where bc = WALL:
                                 T > 0 and no velocity along the wall's normal */
+  double accel[2];           /* body-force acceleration a (App. D), 0 = none; dim 2 and
+                                POND_D2Q16 only.  Each step is wrapped in two half steps
+                                f~ += (dt/2) rho W a.c / sqrt(T) (comoving frame, explicit
+                                Euler), each followed by the move to the new comoving
+                                frame: momentum gains (dt/2) rho a per half step */
 } pond_config;
 
 typedef struct pond_state pond_state;

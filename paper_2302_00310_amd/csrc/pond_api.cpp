@@ -73,6 +73,10 @@ int validate(const pond_config* c) {
       return fail(POND_ERR_INVALID, "a wall needs a positive temperature and a finite velocity");
     if (w[k < 2 ? 0 : 1] != 0.0) return fail(POND_ERR_INVALID, "a wall cannot move along its normal");
   }
+  if (!std::isfinite(c->accel[0]) || !std::isfinite(c->accel[1]))
+    return fail(POND_ERR_INVALID, "the body force must be finite");
+  if ((c->accel[0] != 0.0 || c->accel[1] != 0.0) && (c->dim != 2 || c->lattice != POND_D2Q16))
+    return fail(POND_ERR_UNSUPPORTED, "a body force needs dim 2 and the D2Q16 f-lattice");
   for (int k = 0; k < nside; k += 2)
     if ((c->bc[k] == POND_BC_PERIODIC) != (c->bc[k + 1] == POND_BC_PERIODIC))
       return fail(POND_ERR_INVALID, "a periodic axis needs periodic conditions on both sides");
@@ -346,6 +350,9 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   a.inflow = s->inflow_dev;
   a.cells = n;
   a.flag = s->flag;
+  a.force = (c.accel[0] != 0.0 || c.accel[1] != 0.0) ? 1 : 0;
+  a.hax = 0.5 * s->dt * c.accel[0];
+  a.hay = 0.5 * s->dt * c.accel[1];
   if (s->L.wall_bytes) {
     a.wU = s->wU;
     a.wN = s->wN;

@@ -64,6 +64,8 @@ struct StepArgs {
   double idx2;             // 1 / (2 dx)
   double tau1, tau2;       // relaxation times (tau2 = tau1 / Pr)
   double kf;               // 1 + dt / (2 tau1): non-equilibrium scaling of the stored variable
+  int force;               // 1: body force (2D, D2Q16)
+  double hax, hay;         // (dt/2) a: body-force acceleration times half a step
 };
 
 // One solve of a batched step launch: the arguments of its even and odd

@@ -545,10 +545,13 @@ __device__ __forceinline__ constexpr T wg(int i) {
 
 // Conserved moments and non-equilibrium populations of grid cell (gx, gy),
 // which may lie outside the grid: ghost cells follow the boundary rules.
+// Returns what the slot holds: a cell of the grid (periodic and
+// zero-gradient ghosts are copies of one), an inflow ghost or a wall ghost.
 // WALLS = false: the caller never asks for a wall ghost (cells of the grid,
 // or solves on per-cell f-lattices, which take no walls).
+enum SlotKind { SLOT_CELL = 0, SLOT_INFLOW = 1, SLOT_WALL = 2 };
 template <int D, typename T, bool WALLS = true>
-__device__ __forceinline__ bool load_cell(const StepArgs& a, int gx, int gy, long long (&U)[4],
+__device__ __forceinline__ int load_cell(const StepArgs& a, int gx, int gy, long long (&U)[4],
                                           T (&n)[Geo<D>::NP]) {
   constexpr int NP = Geo<D>::NP;
   int side = -1;
@@ -577,7 +580,7 @@ __device__ __forceinline__ bool load_cell(const StepArgs& a, int gx, int gy, lon
       for (int q = 0; q < 4; ++q) U[q] = a.wU[q * a.wall_n + e];
 #pragma unroll
       for (int i = 0; i < NP; ++i) n[i] = wn[i * a.wall_n + e];
-      return true;
+      return SLOT_WALL;
     }
   }
   if (side >= 0) {
@@ -585,7 +588,7 @@ __device__ __forceinline__ bool load_cell(const StepArgs& a, int gx, int gy, lon
     for (int q = 0; q < 4; ++q) U[q] = a.inflow[4 * side + q];
 #pragma unroll
     for (int i = 0; i < NP; ++i) n[i] = T(0);
-    return false;
+    return SLOT_INFLOW;
   }
   const T* nin = static_cast<const T*>(a.n_in);
   const size_t cell = size_t(sx) + size_t(a.nx) * size_t(sy);
@@ -593,7 +596,48 @@ __device__ __forceinline__ bool load_cell(const StepArgs& a, int gx, int gy, lon
   for (int q = 0; q < 4; ++q) U[q] = a.U_in[q * a.cells + cell];
 #pragma unroll
   for (int i = 0; i < NP; ++i) n[i] = nin[i * a.cells + cell];
-  return false;
+  return SLOT_CELL;
+}
+
+// Body force (App. D), one Strang half step of d f / dt = F with
+// F_i = a . (v_i - u) / T f^eq_i by an explicit Euler step of dt/2 (the
+// sign that makes the force add (dt/2) rho a of momentum, as u* = u +
+// (dt/2) a states).  In the comoving frame (v - u)/T = c / sqrt(T) and
+// f^eq = rho W, so the step adds rho W_i (dt/2) a.c_i / sqrt(T) to f~ and
+// changes the ledger by (dt/2) rho a (momentum) and (dt/2) a.(rho u)
+// (energy); the cell then moves to the comoving frame of its new moments.
+// force_ledger: the ledger part only (ha = (dt/2) a).
+__device__ __forceinline__ void force_ledger(const StepArgs& a, long long (&U)[4], int* bad) {
+  const double rho = double(U[0]) * a.inv_scale;
+  const double mx = double(U[1]) * a.inv_scale, my = double(U[2]) * a.inv_scale;
+  U[1] += to_fixed(rho * a.hax, a.scale, bad);
+  U[2] += to_fixed(rho * a.hay, a.scale, bad);
+  U[3] += to_fixed(a.hax * mx + a.hay * my, a.scale, bad);
+}
+
+template <typename T, int TF>
+__device__ __forceinline__ void force_half(const StepArgs& a, long long (&U)[4], T (&n)[25]) {
+  const Frame f0 = gauge(U, a);
+  int bad = 0;
+  force_ledger(a, U, &bad);
+  raise_flag(a.flag, bad != 0, 2);
+  const Frame f1 = gauge(U, a);
+  const T r = T(f0.rho), kx = T(a.hax * f0.irt), ky = T(a.hay * f0.irt);
+  const T rg0 = T(a.geq * f0.T * f0.rho), rg1 = T(a.geq * f1.T * f1.rho);
+  T ft[16], gt[9], o[25];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const T w = wf<2, T>(i);
+    ft[i] = r * w * (T(1) + kx * node<4, T>(i & 3) + ky * node<4, T>(i >> 2)) + n[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) gt[i] = rg0 * wg<2, T>(i) + n[16 + i];
+  transform<2, 4, T, TF>(f0.rt, f0.ux, f0.uy, f1.irt, f1.ux, f1.uy, ft, o);
+  transform<2, 3, T, TF>(f0.rt, f0.ux, f0.uy, f1.irt, f1.ux, f1.uy, gt, o + 16);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) n[i] = o[i] - r * wf<2, T>(i);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) n[16 + i] = o[16 + i] - rg1 * wg<2, T>(i);
 }
 
 // f-lattice of grid cell (gx, gy) for this step (multiscale kernels): the
@@ -1544,6 +1588,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
     long long U[4];
     T own[NP];
     load_cell<D, T, false>(a, x0 + cx, y0 + cy, U, own);
+    if constexpr (D == 2)
+      if (a.force) force_half<T, TF>(a, U, own);  // as in the loader
     const Frame f0 = gauge(U, a);  // the frame the populations are written in
     qe_half<D, T>(own, own + QF, kappa);
     const T b = T(a.b_upd), lam = T(a.lam);
@@ -1569,6 +1615,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
 #pragma unroll
     for (int i = 0; i < QG; ++i) n2[QF + i] -= rg2 * wg<D, T>(i);
     qe_half<D, T>(n2, n2 + QF, kappa);
+    // second body-force half step
+    if constexpr (D == 2)
+      if (a.force) force_half<T, TF>(a, U2, n2);
     raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
     bool over = false;
 #pragma unroll
@@ -1607,9 +1656,13 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     long long U[4];
     T n[NP];
     // a wall ghost is built at the start of the step with its relaxed
-    // non-equilibrium: the first QE half step does not act on it
-    const bool wall = load_cell<D, T, MS == 0>(a, gx, gy, U, n);
-    const T kap = wall ? T(0) : kappa;
+    // non-equilibrium: the first QE half step does not act on it.  The
+    // first body-force half step acts on the cells of the grid (the ghosts
+    // of walls and inflow sides are built from the forced state or fixed).
+    const int kind = load_cell<D, T, MS == 0>(a, gx, gy, U, n);
+    if constexpr (D == 2 && MS == 0)
+      if (a.force && kind == SLOT_CELL) force_half<T, TF>(a, U, n);
+    const T kap = kind == SLOT_WALL ? T(0) : kappa;
     const Frame fr = gauge(U, a);
     const int h = hx + G::HX * hy;
     const T r = T(fr.rho), rg = T(a.geq * fr.T * fr.rho);
@@ -1798,6 +1851,9 @@ __device__ __forceinline__ Prim wall_field(const StepArgs& a, int side, int m, i
   long long u[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) u[q] = a.U_in[q * a.cells + cell];
+  // the ghosts follow the cells after the first body-force half step
+  int bad = 0;
+  if (a.force) force_ledger(a, u, &bad);
   const Frame f = gauge(u, a);
   Prim p{f.rho, f.ux, f.uy, f.T};
   if (m < 0) {

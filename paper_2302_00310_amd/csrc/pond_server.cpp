@@ -409,6 +409,8 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
   for (int k = 0; k < 4; ++k)
     if (c.bc[k] == POND_BC_WALL) return fail(POND_ERR_UNSUPPORTED, "serving runs solves without walls");
+  if (c.accel[0] != 0.0 || c.accel[1] != 0.0)
+    return fail(POND_ERR_UNSUPPORTED, "serving runs solves without a body force");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");
   const size_t need = layout_of(&c).total;

@@ -37,7 +37,7 @@ class pond_config(C.Structure):
                 ("tau", C.c_double), ("prandtl", C.c_double), ("cfl", C.c_double),
                 ("dx", C.c_double), ("bc", C.c_int * 4), ("inflow", (C.c_double * 4) * 4),
                 ("limiter", C.c_int), ("n_corr", C.c_int), ("ms_threshold", C.c_double),
-                ("wall", (C.c_double * 3) * 4)]
+                ("wall", (C.c_double * 3) * 4), ("accel", C.c_double * 2)]
 
 
 _dbl = C.POINTER(C.c_double)
@@ -228,6 +228,9 @@ def make_config(wl, precision=POND_FP64, transform=POND_TF_LAGRANGE, limiter=PON
         for k in range(4):
             for m in range(3):
                 c.wall[k][m] = float(wall[k][m])
+    accel = getattr(wl, "accel", None)
+    if accel is not None:
+        c.accel[0], c.accel[1] = float(accel[0]), float(accel[1])
     c.limiter, c.n_corr = limiter, n_corr
     return c
 

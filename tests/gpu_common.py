@@ -26,14 +26,23 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def moment_errors(gpu_m, ora_m, l2=False):
-    """Errors on rho, (u_x, u_y) jointly, T."""
+def moment_errors(gpu_m, ora_m, l2=False, u_floor=None):
+    """Errors on rho, (u_x, u_y) jointly, T.  u_floor: a velocity scale under
+    which the velocity error is taken relative to it (a flow that starts at
+    rest has |u| far below its thermal speed, the scale of its rounding)."""
     r_g, ux_g, uy_g, T_g = gpu_m
     r_o, ux_o, uy_o, T_o = ora_m
     f = rel_l2 if l2 else rel_err
     u_g = np.stack([ux_g, uy_g])
     u_o = np.stack([ux_o, uy_o])
-    return {"rho": f(r_g, r_o), "u": f(u_g, u_o), "T": f(T_g, T_o)}
+    eu = f(u_g, u_o)
+    if u_floor is not None:
+        scale = np.linalg.norm(u_o) if l2 else np.max(np.abs(u_o))
+        if l2:
+            eu = float(np.linalg.norm(u_g - u_o) / max(scale, u_floor * np.sqrt(u_o.size)))
+        else:
+            eu = float(np.max(np.abs(u_g - u_o)) / max(scale, u_floor))
+    return {"rho": f(r_g, r_o), "u": eu, "T": f(T_g, T_o)}
 
 
 def window_samples(wl, points, steps, transform=0, n_corr=0, limiter=0, flat=0,

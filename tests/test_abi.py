@@ -140,3 +140,17 @@ def test_wall_config_rules(pond):
     c = pond.make_config(wl)
     c.bc[2] = 4
     assert pond.pond_state_bytes(c) == 0
+
+
+def test_body_force_config_rules(pond):
+    """A body force needs 2D and the D2Q16 f-lattice (else unsupported) and
+    finite components."""
+    wl = inputs.poiseuille_2d(ny=32, nx=8)
+    assert pond.pond_state_bytes(pond.make_config(wl)) > 0
+    bad = pond.make_config(wl, transform=1, lattice=pond.POND_D2Q9)
+    bad.bc[2] = bad.bc[3] = 0
+    h = C.c_void_p()
+    assert pond.load_library().pond_create(C.byref(bad), None, 0, None, C.byref(h)) == -6
+    c = pond.make_config(wl)
+    c.accel[1] = float("inf")
+    assert pond.pond_state_bytes(c) == 0
