@@ -38,10 +38,10 @@ BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
 KERNEL_SOURCES = ("paper_2302_00310_amd/csrc/pond_kernels.hip",
                   "paper_2302_00310_amd/csrc/pond_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "d08e7fec9ff846e5dbca30dcb93e228f197961c7a20a3da40b1956e91df96b0a",
+    "sha256": "fc2cacd4f77a11645b3ab735e05cd2344639018ffc4bdf1dc51f32302290a568",
     "n": 2048,
-    "fetch_bytes": 1.65231e+09,
-    "write_bytes": 7.88966e+08,
+    "fetch_bytes": 1.65020e+09,
+    "write_bytes": 7.85312e+08,
 }
 
 

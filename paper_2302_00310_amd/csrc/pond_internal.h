@@ -52,7 +52,7 @@ struct StepArgs {
   // the lattice n_in is written in, and the one this step uses and writes
   const unsigned char* lat_in;
   const unsigned char* lat_out;
-  int ms;                  // 1: per-cell f-lattices (D2Q9 or multiscale)
+  int ms;                  // kernel mode: 0 D2Q16, 1 per-cell f-lattices, 2 D2Q16 with walls or force
   // walls: ghost layer k (1, 2) of side s at coordinate t along the wall is
   // entry (2 s + k - 1) wall_len + t of wall_n-long planes, written before
   // each step by the wall-ghost kernel and read by the tile loader
@@ -77,8 +77,10 @@ struct BatchEntry {
 };
 
 // Host-side launchers (defined in pond_kernels.hip).
-// Step kernels by kind: transform t (0 Lagrange, 1 Grad) and per-cell
-// f-lattices ms (0: D2Q16 everywhere, 1: D2Q9 or multiscale, Grad only).
+// Step kernels by kind: transform t (0 Lagrange, 1 Grad) and mode ms (0:
+// D2Q16 everywhere; 1: per-cell f-lattices, D2Q9 or multiscale, Grad only;
+// 2: D2Q16 with walls or a body force -- their loader and update carry the
+// extra work, which the plain kernels leave out).
 constexpr int kind_of(int transform, int ms) { return transform + 2 * ms; }
 // kind_mask: bit kind_of(t, ms) set launches that kernel (a batch may hold
 // solves of several kinds; each kernel skips the others' blocks).

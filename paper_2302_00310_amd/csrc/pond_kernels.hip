@@ -1472,8 +1472,9 @@ __device__ __forceinline__ void step_update_ms(const StepArgs& a, int x, int y,
 // The fused step kernel.
 // --------------------------------------------------------------------------
 // Phases 1-5 of a tile (faces, gathers, update) after its halo is loaded.
-// M: the f-lattice mode of the faces (see face_eval).
-template <int D, typename T, int LIM, int TF, int M>
+// M: the f-lattice mode of the faces (see face_eval).  EXT: the solve may
+// carry a body force (D2Q16 solves with walls or a force run this variant).
+template <int D, typename T, int LIM, int TF, int M, bool EXT = false>
 __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int tid, int x0, int y0,
                                           T kappa) {
   using G = Geo<D>;
@@ -1588,7 +1589,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
     long long U[4];
     T own[NP];
     load_cell<D, T, false>(a, x0 + cx, y0 + cy, U, own);
-    if constexpr (D == 2)
+    if constexpr (D == 2 && EXT)
       if (a.force) force_half<T, TF>(a, U, own);  // as in the loader
     const Frame f0 = gauge(U, a);  // the frame the populations are written in
     qe_half<D, T>(own, own + QF, kappa);
@@ -1616,7 +1617,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
     for (int i = 0; i < QG; ++i) n2[QF + i] -= rg2 * wg<D, T>(i);
     qe_half<D, T>(n2, n2 + QF, kappa);
     // second body-force half step
-    if constexpr (D == 2)
+    if constexpr (D == 2 && EXT)
       if (a.force) force_half<T, TF>(a, U2, n2);
     raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
     bool over = false;
@@ -1632,6 +1633,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
   }
 }
 
+// MS: 0 D2Q16; 1 per-cell f-lattices; 2 D2Q16 with walls or a body force.
 template <int D, typename T, int LIM, int TF, int MS = 0>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
@@ -1659,14 +1661,14 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     // non-equilibrium: the first QE half step does not act on it.  The
     // first body-force half step acts on the cells of the grid (the ghosts
     // of walls and inflow sides are built from the forced state or fixed).
-    const int kind = load_cell<D, T, MS == 0>(a, gx, gy, U, n);
-    if constexpr (D == 2 && MS == 0)
+    const int kind = load_cell<D, T, MS == 2>(a, gx, gy, U, n);
+    if constexpr (D == 2 && MS == 2)
       if (a.force && kind == SLOT_CELL) force_half<T, TF>(a, U, n);
     const T kap = kind == SLOT_WALL ? T(0) : kappa;
     const Frame fr = gauge(U, a);
     const int h = hx + G::HX * hy;
     const T r = T(fr.rho), rg = T(a.geq * fr.T * fr.rho);
-    if constexpr (D == 2 && MS) {
+    if constexpr (D == 2 && MS == 1) {
       // multiscale: the slot's f-lattice for this step; populations stored
       // on another lattice are lifted or projected first
       int qn, qo;
@@ -1695,7 +1697,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
   __syncthreads();
   // phases 1-5; with per-cell f-lattices a tile whose halo is all D2Q9 or
   // all D2Q16 runs a body specialised to that lattice
-  if constexpr (D == 2 && MS != 0) {
+  if constexpr (D == 2 && MS == 1) {
     bool has16 = false, has9 = false;
     for (int k = tid; k < G::NH; k += kThreads) {
       has16 |= sm.Lat[k] == 4;
@@ -1706,7 +1708,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     else if (!any16) step_body<D, T, LIM, TF, 3>(a, sm, tid, x0, y0, kappa);
     else step_body<D, T, LIM, TF, 1>(a, sm, tid, x0, y0, kappa);
   } else {
-    step_body<D, T, LIM, TF, 0>(a, sm, tid, x0, y0, kappa);
+    step_body<D, T, LIM, TF, 0, MS == 2>(a, sm, tid, x0, y0, kappa);
   }
 }
 
@@ -2028,6 +2030,14 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
   if (kind_mask & (1u << kind_of(TF_GRAD, 0))) {
     if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 0>), grid, block, 0, st, tab, n, parity);
     else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 0>), grid, block, 0, st, tab, n, parity);
+  }
+  if (kind_mask & (1u << kind_of(TF_LAGRANGE, 2))) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_LAGRANGE, 2>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_LAGRANGE, 2>), grid, block, 0, st, tab, n, parity);
+  }
+  if (kind_mask & (1u << kind_of(TF_GRAD, 2))) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 2>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 2>), grid, block, 0, st, tab, n, parity);
   }
   if (kind_mask & (1u << kind_of(TF_GRAD, 1))) {
     if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 1>), grid, block, 0, st, tab, n, parity);
