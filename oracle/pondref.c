@@ -32,8 +32,8 @@ const char* pondref_last_error(void) { return g_err; }
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int q;
-  double c[4];
-  double w[4];
+  double c[5];
+  double w[5];
 } lat1;
 
 static void lattice_d1q4(lat1* L) {
@@ -54,12 +54,32 @@ static void lattice_d1q3(lat1* L) {
   L->w[0] = 1.0 / 6.0; L->w[1] = 2.0 / 3.0; L->w[2] = 1.0 / 6.0; L->w[3] = 0.0;
 }
 
-static void lattice_get(int which, lat1* L) {
-  if (which == 0) lattice_d1q4(L); else lattice_d1q3(L);
+/* D1Q5: the five-point Gauss--Hermite rule, nodes 0, +-sqrt(5 -+ sqrt 10),
+   weights 8/15 and (7 +- 2 sqrt 10)/60 (the 1D factor of D2Q25, Table I). */
+static void lattice_d1q5(lat1* L) {
+  const double s10 = sqrt(10.0);
+  const double a = sqrt(5.0 - s10), b = sqrt(5.0 + s10);
+  L->q = 5;
+  L->c[0] = -b; L->c[1] = -a; L->c[2] = 0.0; L->c[3] = a; L->c[4] = b;
+  L->w[0] = (7.0 - 2.0 * s10) / 60.0;
+  L->w[1] = (7.0 + 2.0 * s10) / 60.0;
+  L->w[2] = 8.0 / 15.0;
+  L->w[3] = (7.0 + 2.0 * s10) / 60.0;
+  L->w[4] = (7.0 - 2.0 * s10) / 60.0;
 }
 
+/* 0: D1Q4, 1: D1Q3, 2: D1Q5 */
+static void lattice_get(int which, lat1* L) {
+  if (which == 0) lattice_d1q4(L);
+  else if (which == 1) lattice_d1q3(L);
+  else lattice_d1q5(L);
+}
+
+/* lattice_get index of the 1D rule with q nodes */
+static int lat_of_q(int q) { return q == 4 ? 0 : (q == 3 ? 1 : 2); }
+
 int pondref_lattice(int lattice, double* c, double* w) {
-  if (lattice != 0 && lattice != 1) return fail("lattice must be 0 (D1Q4) or 1 (D1Q3)");
+  if (lattice < 0 || lattice > 2) return fail("lattice must be 0 (D1Q4), 1 (D1Q3) or 2 (D1Q5)");
   lat1 L;
   lattice_get(lattice, &L);
   for (int k = 0; k < L.q; k++) { c[k] = L.c[k]; w[k] = L.w[k]; }
@@ -122,7 +142,7 @@ static int solve_dense(int n, double* A, double* B, int m) {
    sum_k c_k^a G1[k][m] = xi_m^a, a = 0..q-1, xi_m = s c_m + d. */
 static int tf1_lagrange(const lat1* L, double s, double d, double* G1) {
   const int q = L->q;
-  double V[16], X[16];
+  double V[25], X[25];
   for (int a = 0; a < q; a++)
     for (int k = 0; k < q; k++) {
       V[a * q + k] = ipow(L->c[k], a);
@@ -163,7 +183,7 @@ static int transform_matrix(int dim, const lat1* L, int transform, const double 
   double s, dx, dy;
   frame_shift(src, dst, &s, &dx, &dy);
   if (transform == PONDREF_TF_LAGRANGE) {
-    double Gx[16], Gy[16];
+    double Gx[25], Gy[25];
     if (tf1_lagrange(L, s, dx, Gx)) return -1;
     if (dim == 1) {
       memcpy(G, Gx, sizeof(double) * q * q);
@@ -197,16 +217,23 @@ static int transform_matrix(int dim, const lat1* L, int transform, const double 
     return 0;
   }
   const int Q = q * q;
+  /* the Hermite values at the target nodes and at the shifted source nodes,
+     tabulated once (the same numbers the sum below would evaluate) */
+  double hc[5][5], hx[5][5], hy[5][5];
+  for (int a = 0; a <= K; a++)
+    for (int k = 0; k < q; k++) {
+      hc[a][k] = hermite(a, L->c[k]);
+      hx[a][k] = hermite(a, s * L->c[k] + dx);
+      hy[a][k] = hermite(a, s * L->c[k] + dy);
+    }
   for (int ky = 0; ky < q; ky++)
     for (int kx = 0; kx < q; kx++)
       for (int my = 0; my < q; my++)
         for (int mx = 0; mx < q; mx++) {
-          const double xm = s * L->c[mx] + dx, ym = s * L->c[my] + dy;
           double acc = 0.0;
           for (int a = 0; a <= K; a++)
             for (int b = 0; a + b <= K; b++)
-              acc += hermite(a, L->c[kx]) * hermite(b, L->c[ky]) * hermite(a, xm) *
-                     hermite(b, ym) / (factorial[a] * factorial[b]);
+              acc += hc[a][kx] * hc[b][ky] * hx[a][mx] * hy[b][my] / (factorial[a] * factorial[b]);
           G[(kx + q * ky) * Q + (mx + q * my)] = L->w[kx] * L->w[ky] * acc;
         }
   return 0;
@@ -215,7 +242,7 @@ static int transform_matrix(int dim, const lat1* L, int transform, const double 
 int pondref_transform_matrix(int dim, int lattice, int transform, const double src[3],
                              const double dst[3], double* G) {
   if (dim != 1 && dim != 2) return fail("dim must be 1 or 2");
-  if (lattice != 0 && lattice != 1) return fail("lattice must be 0 or 1");
+  if (lattice < 0 || lattice > 2) return fail("lattice must be 0, 1 or 2");
   if (src[2] <= 0.0 || dst[2] <= 0.0) return fail("frame temperature must be positive");
   lat1 L;
   lattice_get(lattice, &L);
@@ -272,8 +299,8 @@ int pondref_transform_matrix_full(int dim, int lattice, const double src[3],
 static int ms_matrix(int transform, int q1s, const double src[3], int q1t, const double dst[3],
                      double* G) {
   lat1 Ls, Lt;
-  lattice_get(q1s == 4 ? 0 : 1, &Ls);
-  lattice_get(q1t == 4 ? 0 : 1, &Lt);
+  lattice_get(lat_of_q(q1s), &Ls);
+  lattice_get(lat_of_q(q1t), &Lt);
   if (q1s == q1t) return transform_matrix(2, &Ls, transform, src, dst, G);
   if (q1s == 3) {
     /* lifting: own-frame D2Q16 expansion with alpha_ab (a + b <= 2) from the
@@ -346,12 +373,12 @@ static void matvec(int Q, const double* G, const double* in, double* out) {
 /* ------------------------------------------------------------------------ */
 #define NG 2 /* ghost layers */
 #define TIE_BAND 1e-11 /* |v_n| <= TIE_BAND sqrt(T_F) is an upwind tie */
-#define QMAX 16
+#define QMAX 25
 
 struct pondref_state {
   pondref_config cfg;
   int D;
-  lat1 Lf, Lg;       /* D1Q4 for f, D1Q3 for g */
+  lat1 Lf, Lg;       /* D1Q4 (D1Q5 for the D2Q25 f-lattice) for f, D1Q3 for g */
   int Qf, Qg;
   double Wf[QMAX], Wg[9];
   double cfx[QMAX], cfy[QMAX], cgx[9], cgy[9]; /* lattice velocity components */
@@ -410,8 +437,10 @@ static int check_config(const pondref_config* c) {
   if (c->limiter != PONDREF_LIM_VANLEER && c->limiter != PONDREF_LIM_MINMOD)
     return fail("unknown limiter");
   if (c->n_corr < 0) return fail("n_corr must be >= 0");
-  if (c->flat < 0 || c->flat > 2) return fail("unknown f-lattice");
-  if (c->flat != PONDREF_F_D2Q16 && c->dim != 2) return fail("the D2Q9 and multiscale f-lattices are 2D");
+  if (c->flat < 0 || c->flat > 3) return fail("unknown f-lattice");
+  if (c->flat == PONDREF_F_D2Q25 && c->transform != PONDREF_TF_GRAD)
+    return fail("the D2Q25 f-lattice uses the fourth-order Grad projection");
+  if (c->flat != PONDREF_F_D2Q16 && c->dim != 2) return fail("the D2Q9, multiscale and D2Q25 f-lattices are 2D");
   if (c->flat == PONDREF_F_MULTISCALE && c->transform != PONDREF_TF_GRAD)
     return fail("the multiscale deployment uses Grad's projection");
   if (c->flat == PONDREF_F_MULTISCALE && !(c->ms_threshold >= 0.0))
@@ -445,18 +474,20 @@ int pondref_create(const pondref_config* cfg, pondref_state** out) {
   pondref_state* s = (pondref_state*)calloc(1, sizeof(pondref_state));
   s->cfg = *cfg;
   s->D = cfg->dim;
-  lattice_d1q4(&s->Lf);
+  if (cfg->dim == 2 && cfg->flat == PONDREF_F_D2Q25) lattice_d1q5(&s->Lf);
+  else lattice_d1q4(&s->Lf);
   lattice_d1q3(&s->Lg);
   if (s->D == 1) {
     s->Qf = 4; s->Qg = 3;
     for (int i = 0; i < 4; i++) { s->Wf[i] = s->Lf.w[i]; s->cfx[i] = s->Lf.c[i]; s->cfy[i] = 0.0; }
     for (int i = 0; i < 3; i++) { s->Wg[i] = s->Lg.w[i]; s->cgx[i] = s->Lg.c[i]; s->cgy[i] = 0.0; }
   } else {
-    s->Qf = 16; s->Qg = 9;
+    const int q = s->Lf.q;
+    s->Qf = q * q; s->Qg = 9;
     /* eq. (wi): W_i = w_ix w_iy, c_i = (c_ix, c_iy), i = i_x + q i_y */
-    for (int iy = 0; iy < 4; iy++)
-      for (int ix = 0; ix < 4; ix++) {
-        const int i = ix + 4 * iy;
+    for (int iy = 0; iy < q; iy++)
+      for (int ix = 0; ix < q; ix++) {
+        const int i = ix + q * iy;
         s->Wf[i] = s->Lf.w[ix] * s->Lf.w[iy];
         s->cfx[i] = s->Lf.c[ix];
         s->cfy[i] = s->Lf.c[iy];
@@ -469,8 +500,8 @@ int pondref_create(const pondref_config* cfg, pondref_state** out) {
         s->cgy[i] = s->Lg.c[iy];
       }
   }
-  /* per-lattice tables: D2Q16 / D1Q4 (index 0) and the D2Q9 f-lattice
-     (index 1, tensor D1Q3, i = i_x + 3 i_y) */
+  /* per-lattice tables: the solve's f-lattice D2Q16 / D2Q25 / D1Q4 (index
+     0) and the D2Q9 f-lattice (index 1, tensor D1Q3, i = i_x + 3 i_y) */
   s->Qq[0] = s->Qf;
   for (int i = 0; i < s->Qf; i++) { s->Wq[0][i] = s->Wf[i]; s->cxq[0][i] = s->cfx[i]; s->cyq[0][i] = s->cfy[i]; }
   s->Qq[1] = s->Qg;
@@ -480,7 +511,7 @@ int pondref_create(const pondref_config* cfg, pondref_state** out) {
   const size_t nc = (size_t)s->nxp * s->nyp;
   s->lat = (unsigned char*)malloc(nc);
   s->flag = (unsigned char*)calloc(nc, 1);
-  memset(s->lat, cfg->flat == PONDREF_F_D2Q9 ? 3 : 4, nc);
+  memset(s->lat, cfg->flat == PONDREF_F_D2Q9 ? 3 : s->Lf.q, nc);
   s->theta = (double*)calloc((size_t)cfg->nx * cfg->ny, sizeof(double));
   s->f = (double*)calloc(nc * s->Qf, sizeof(double));
   s->g = (double*)calloc(nc * s->Qg, sizeof(double));
@@ -522,7 +553,7 @@ void pondref_destroy(pondref_state* s) {
    (eq. geqPond), written in the comoving frame lambda = {u, T}. */
 static void comoving_eq(const pondref_state* s, int q1, double rho, double T, double* feq,
                         double* geq) {
-  const int l = q1 == 4 ? 0 : 1;
+  const int l = q1 == 3 ? 1 : 0;
   for (int i = 0; i < s->Qq[l]; i++) feq[i] = rho * s->Wq[l][i];
   const double e = (s->cv - 0.5 * s->D) * T * rho;
   for (int i = 0; i < s->Qg; i++) geq[i] = e * s->Wg[i];
@@ -533,7 +564,7 @@ static void comoving_eq(const pondref_state* s, int q1, double rho, double T, do
 static void moments(const pondref_state* s, int q1, const double* f, const double* g,
                     const double fr[3], double* rho, double* ux, double* uy, double* T,
                     double* rhoE) {
-  const int l = q1 == 4 ? 0 : 1;
+  const int l = q1 == 3 ? 1 : 0;
   const double rt = sqrt(fr[2]);
   double m0 = 0.0, mx = 0.0, my = 0.0, e = 0.0;
   for (int i = 0; i < s->Qq[l]; i++) {
@@ -561,7 +592,9 @@ static double cfl_dt(const pondref_config* c, const double* rho, const double* u
   /* CFL = max|v_ia| dt / dx = 0.2 (Sec. V); the max runs over cells,
      populations and axes of |sqrt(T) c_ia + u_a|, at t = 0 (reading). */
   /* the largest node of the f-lattice in use (D2Q9 alone: sqrt 3) */
-  const double cmax = (c->dim == 2 && c->flat == PONDREF_F_D2Q9) ? sqrt(3.0) : sqrt(3.0 + sqrt(6.0));
+  double cmax = sqrt(3.0 + sqrt(6.0));
+  if (c->dim == 2 && c->flat == PONDREF_F_D2Q9) cmax = sqrt(3.0);
+  if (c->dim == 2 && c->flat == PONDREF_F_D2Q25) cmax = sqrt(5.0 + sqrt(10.0));
   const double dx = c->dx > 0.0 ? c->dx : 1.0 / c->nx;
   double vmax = 0.0;
   const size_t n = (size_t)c->nx * c->ny;
@@ -899,7 +932,7 @@ static void qe_half_step(const pondref_state* s, int q1, double* f, double* g) {
   }
   /* H^(3)_{abc}(c) = c_a c_b c_c - [c_a delta_bc]_cyc (App. A) */
   double axxx = 0.0, axxy = 0.0, axyy = 0.0, ayyy = 0.0, agx = 0.0, agy = 0.0;
-  for (int i = 0; i < 16; i++) {
+  for (int i = 0; i < s->Qf; i++) {
     const double cx = s->cfx[i], cy = s->cfy[i];
     axxx += f[i] * (cx * cx * cx - 3.0 * cx);
     axxy += f[i] * (cx * cx * cy - cy);
@@ -907,7 +940,7 @@ static void qe_half_step(const pondref_state* s, int q1, double* f, double* g) {
     ayyy += f[i] * (cy * cy * cy - 3.0 * cy);
   }
   for (int i = 0; i < 9; i++) { agx += g[i] * s->cgx[i]; agy += g[i] * s->cgy[i]; }
-  for (int i = 0; i < 16; i++) {
+  for (int i = 0; i < s->Qf; i++) {
     const double cx = s->cfx[i], cy = s->cfy[i];
     const double contr = axxx * (cx * cx * cx - 3.0 * cx) + 3.0 * axxy * (cx * cx * cy - cy) +
                          3.0 * axyy * (cx * cy * cy - cx) + ayyy * (cy * cy * cy - 3.0 * cy);
@@ -935,7 +968,7 @@ static double limiter(int kind, double a, double b) {
    (1D: the D1Q4 map of the configured transform). */
 static void xf_f(const pondref_state* s, int q1s, const double src[3], int q1t,
                  const double dst[3], const double* in, double* out) {
-  double G[256];
+  double G[QMAX * QMAX];
   if (s->D == 1) {
     transform_matrix(1, &s->Lf, s->cfg.transform, src, dst, G);
     matvec(4, G, in, out);
@@ -971,7 +1004,7 @@ static void face_flux(const pondref_state* s, const face_stencil* st, double* fo
      D2Q16 regions extend to their boundary faces (the stencil's other
      cells are lifted or projected into it) */
   const int qF = s->lat[st->L] > s->lat[st->R] ? s->lat[st->L] : s->lat[st->R];
-  const int lq = qF == 4 ? 0 : 1;
+  const int lq = qF == 3 ? 1 : 0;
   const int QF = s->Qq[lq];
   const double* fcx = s->cxq[lq];
   const double* fcy = s->cyq[lq];
@@ -1141,7 +1174,7 @@ static void one_step(pondref_state* s) {
       const int c = cidx(s, x, y);
       const double* f = s->f + (size_t)c * Qf;
       const double* g = s->g + (size_t)c * Qg;
-      const int Qc = s->Qq[s->lat[c] == 4 ? 0 : 1];
+      const int Qc = s->Qq[s->lat[c] == 3 ? 1 : 0];
       double rho = 0.0;
       for (int i = 0; i < Qc; i++) rho += f[i];
       double feq[QMAX] = {0}, geq[9];
@@ -1197,7 +1230,7 @@ static void one_step(pondref_state* s) {
       double Gg[81];
       double flf[QMAX] = {0}, flg[9] = {0}, tf[QMAX] = {0}, tg[9];
       const double rt = sqrt(fr[2]);
-      const int qc = s->lat[c], lc = qc == 4 ? 0 : 1, Qc = s->Qq[lc];
+      const int qc = s->lat[c], lc = qc == 3 ? 1 : 0, Qc = s->Qq[lc];
       const int nface = twod ? 4 : 2;
       for (int k = 0; k < nface; k++) {
         /* faces: west (-x), east (+x), south (-y), north (+y) */

@@ -31,9 +31,11 @@ enum { PONDREF_TF_LAGRANGE = 0, PONDREF_TF_GRAD = 1 };
 enum { PONDREF_BC_PERIODIC = 0, PONDREF_BC_ZERO_GRADIENT = 1, PONDREF_BC_INFLOW = 2,
        PONDREF_BC_WALL = 3 };
 enum { PONDREF_LIM_VANLEER = 0, PONDREF_LIM_MINMOD = 1 };
-/* 2D f-lattice (Sec. III C): D2Q16 everywhere, D2Q9 everywhere, or the
-   multiscale D2Q9/D2Q16 deployment chosen cell by cell (Sec. IV C). */
-enum { PONDREF_F_D2Q16 = 0, PONDREF_F_D2Q9 = 1, PONDREF_F_MULTISCALE = 2 };
+/* 2D f-lattice (Sec. III C): D2Q16 everywhere, D2Q9 everywhere, the
+   multiscale D2Q9/D2Q16 deployment chosen cell by cell (Sec. IV C), or
+   D2Q25 everywhere with the fourth-order Grad projection (Sec. III B, the
+   full invariant moment system; Sec. V shock structure). */
+enum { PONDREF_F_D2Q16 = 0, PONDREF_F_D2Q9 = 1, PONDREF_F_MULTISCALE = 2, PONDREF_F_D2Q25 = 3 };
 
 typedef struct {
   int dim, nx, ny;          /* ny = 1 when dim = 1 */
@@ -84,7 +86,8 @@ int pondref_set_threads(int n);
 int pondref_get_threads(void);
 
 /* Building blocks exposed for pin tests.
-   lattice: 0 = D1Q4 (f), 1 = D1Q3 (g).  Nodes and weights in ascending order. */
+   lattice: 0 = D1Q4 (f), 1 = D1Q3 (g), 2 = D1Q5 (f of D2Q25).  Nodes and
+   weights in ascending order. */
 int pondref_lattice(int lattice, double* c, double* w);
 /* Dense transform matrix G (Q x Q, row = target population) mapping
    populations written in frame src = (u_x, u_y, T) to frame dst, for the

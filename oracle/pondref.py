@@ -11,7 +11,7 @@ _LIB = None
 
 TF_LAGRANGE, TF_GRAD = 0, 1
 LIM_VANLEER, LIM_MINMOD = 0, 1
-F_D2Q16, F_D2Q9, F_MULTISCALE = 0, 1, 2
+F_D2Q16, F_D2Q9, F_MULTISCALE, F_D2Q25 = 0, 1, 2, 3
 MS_THRESHOLD = 0.05  # default switch threshold of the multiscale deployment
 
 
@@ -101,15 +101,18 @@ def get_threads() -> int:
     return load_library().pondref_get_threads()
 
 
+_Q1 = {0: 4, 1: 3, 2: 5}   # nodes of lattice_get's rules: D1Q4, D1Q3, D1Q5
+
+
 def lattice(which: int):
-    c = np.zeros(4)
-    w = np.zeros(4)
+    c = np.zeros(5)
+    w = np.zeros(5)
     q = _check(load_library().pondref_lattice(which, c, w))
     return c[:q].copy(), w[:q].copy()
 
 
 def transform_matrix(dim, which, src, dst, transform=TF_LAGRANGE):
-    q = 4 if which == 0 else 3
+    q = _Q1[which]
     Q = q ** dim
     G = np.zeros(Q * Q)
     _check(load_library().pondref_transform_matrix(dim, which, transform,
@@ -118,7 +121,7 @@ def transform_matrix(dim, which, src, dst, transform=TF_LAGRANGE):
 
 
 def transform_matrix_full(dim, which, src, dst):
-    q = 4 if which == 0 else 3
+    q = _Q1[which]
     Q = q ** dim
     G = np.zeros(Q * Q)
     _check(load_library().pondref_transform_matrix_full(dim, which, np.ascontiguousarray(src, float),
@@ -158,7 +161,7 @@ class Oracle:
         _check(self.lib.pondref_create(C.byref(self.cfg), C.byref(h)))
         self.h = h
         self.dim, self.nx, self.ny = wl.dim, wl.nx, wl.ny
-        self.Qf, self.Qg = (4, 3) if wl.dim == 1 else (16, 9)
+        self.Qf, self.Qg = (4, 3) if wl.dim == 1 else (25 if flat == F_D2Q25 else 16, 9)
         if dt is not None:
             _check(self.lib.pondref_set_dt(self.h, float(dt)))
         if init:
