@@ -55,7 +55,13 @@ enum {
 };
 
 /* f-lattice (the g-lattice is D1Q3 / D2Q9), Table I */
-enum { POND_D1Q4 = 1, POND_D2Q16 = 2, POND_D2Q9 = 3, POND_D2Q9_D2Q16 = 4 };
+enum { POND_D1Q4 = 1, POND_D2Q16 = 2, POND_D2Q9 = 3, POND_D2Q9_D2Q16 = 4, POND_D2Q25 = 5 };
+/* POND_D2Q25: the fourth-order f-lattice (tensor of the 5-point
+   Gauss-Hermite rule, Table I) with the fourth-order Grad projection
+   (Sec. III B, full invariant moment system): needs POND_TF_GRAD and dim 2;
+   no walls or body force.  Runs as three plain kernels per step with the
+   face data in the arena (not fused like D2Q16), not in the serving loop,
+   and pond_export_state does not cover it. */
 /* POND_D2Q9: the second-order f-lattice everywhere.  POND_D2Q9_D2Q16: the
    multiscale deployment (Sec. III C, Sec. IV C) -- each step, D2Q16 within
    two cells of a cell whose gradient indicator

@@ -42,8 +42,11 @@ int validate(const pond_config* c) {
     return fail(POND_ERR_INVALID, "grid needs nx >= 4 and, in 2D, ny >= 4 (ny = 1 in 1D)");
   if ((c->dim == 1 && c->lattice != POND_D1Q4) ||
       (c->dim == 2 && c->lattice != POND_D2Q16 && c->lattice != POND_D2Q9 &&
-       c->lattice != POND_D2Q9_D2Q16))
-    return fail(POND_ERR_INVALID, "lattice must be D1Q4 in 1D and D2Q16, D2Q9 or D2Q9_D2Q16 in 2D");
+       c->lattice != POND_D2Q9_D2Q16 && c->lattice != POND_D2Q25))
+    return fail(POND_ERR_INVALID,
+                "lattice must be D1Q4 in 1D and D2Q16, D2Q9, D2Q9_D2Q16 or D2Q25 in 2D");
+  if (c->lattice == POND_D2Q25 && c->transform != POND_TF_GRAD)
+    return fail(POND_ERR_INVALID, "the D2Q25 f-lattice uses the fourth-order Grad projection");
   if ((c->lattice == POND_D2Q9 || c->lattice == POND_D2Q9_D2Q16) && c->transform != POND_TF_GRAD)
     return fail(POND_ERR_INVALID, "the D2Q9 and multiscale f-lattices use Grad's projection");
   if (c->lattice == POND_D2Q9_D2Q16 && !(c->ms_threshold >= 0.0 && std::isfinite(c->ms_threshold)))
@@ -92,7 +95,8 @@ int validate(const pond_config* c) {
 Layout layout_of(const pond_config* c) {
   Layout L;
   L.D = c->dim;
-  L.QF = c->dim == 2 ? 16 : 4;
+  L.q25 = c->dim == 2 && c->lattice == POND_D2Q25;
+  L.QF = c->dim == 2 ? (L.q25 ? 25 : 16) : 4;
   L.QG = c->dim == 2 ? 9 : 3;
   L.NP = L.QF + L.QG;
   L.fp64 = c->precision == POND_FP64;
@@ -114,8 +118,18 @@ Layout layout_of(const pond_config* c) {
   // wall ghosts: [side][layer][t] entries, t along the wall (max(nx, ny))
   L.wall_len = walls ? size_t(std::max(c->nx, c->ny)) : 0;
   L.wall_bytes = walls ? align256(size_t(8) * L.wall_len * (4 * sizeof(long long) + L.NP * elt)) : 0;
+  if (L.q25) {
+    L.q25_nfx = size_t(c->nx + 1) * c->ny;
+    L.q25_nfy = size_t(c->nx) * (c->ny + 1);
+    L.q25_P = align256(size_t(L.NP) * L.cells * elt);
+    L.q25_fr = align256(3 * L.cells * sizeof(double));
+    for (size_t nf : {L.q25_nfx, L.q25_nfy})
+      L.q25_bytes += align256(size_t(L.NP) * nf * elt) + align256(3 * nf * sizeof(double)) +
+                     align256(4 * nf * sizeof(long long));
+    L.q25_bytes += L.q25_P + L.q25_fr;
+  }
   L.total = 2 * L.pop_bytes + 2 * L.led_bytes + 512 + L.tab_bytes + L.red_bytes + L.stage_bytes +
-            2 * L.lat_bytes + L.theta_bytes + L.wall_bytes;
+            2 * L.lat_bytes + L.theta_bytes + L.wall_bytes + L.q25_bytes;
   return L;
 }
 
@@ -233,6 +247,18 @@ int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, voi
     s->wU = reinterpret_cast<long long*>(p); p += size_t(8) * L.wall_len * 4 * sizeof(long long);
     s->wN = p;
   }
+  if (L.q25) {
+    p = static_cast<char*>(dev_arena) + (L.total - L.q25_bytes);
+    const size_t elt = L.fp64 ? 8 : 4;
+    s->qP = p; p += L.q25_P;
+    s->qfr = reinterpret_cast<double*>(p); p += L.q25_fr;
+    const size_t nfs[2] = {L.q25_nfx, L.q25_nfy};
+    for (int ax = 0; ax < 2; ++ax) {
+      s->qfp[ax] = p; p += align256(size_t(L.NP) * nfs[ax] * elt);
+      s->qff[ax] = reinterpret_cast<double*>(p); p += align256(3 * nfs[ax] * sizeof(double));
+      s->qps[ax] = reinterpret_cast<long long*>(p); p += align256(4 * nfs[ax] * sizeof(long long));
+    }
+  }
   s->dx = cfg->dx > 0.0 ? cfg->dx : 1.0 / cfg->nx;
   s->cv = 1.0 / (cfg->gamma - 1.0);
   hipError_t e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
@@ -253,7 +279,7 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   if (twod && !uy) return fail(POND_ERR_INVALID, "uy is required in 2D");
   // dt from the CFL rule at t = 0 (Sec. V): max over cells, nodes and axes
   // of |sqrt(T) c_ia + u_a| (largest node of the f-lattice in use)
-  const double cmax = c.lattice == POND_D2Q9 ? kR3 : kB;
+  const double cmax = c.lattice == POND_D2Q9 ? kR3 : (c.lattice == POND_D2Q25 ? kB5 : kB);
   double vmax = 0.0, M = 0.0, U4[4];
   for (size_t k = 0; k < n; ++k) {
     const double vy = twod ? uy[k] : 0.0;
@@ -285,6 +311,8 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
     conserved_of(st[0], st[1], twod ? st[2] : 0.0, st[3], s->cv, U4);
     for (int q = 0; q < 4; ++q) s->inflow_U[k][q] = (long long)std::nearbyint(U4[q] * s->scale);
   }
+  // D2Q25: the init kernel writes the 25 planes of D2Q16; clear the rest
+  if (s->L.q25) POND_HIP(hipMemsetAsync(s->n[0], 0, s->L.pop_bytes, s->stream));
   // upload the primitive fields chunk by chunk and build the equilibrium state
   const size_t chunk = s->L.stage_cells;
   std::vector<double> host(4 * chunk);
@@ -374,7 +402,15 @@ int pond_step(pond_state* s, int nsteps) {
   if (!s || nsteps < 0) return fail(POND_ERR_INVALID, "bad arguments");
   if (!s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
   for (int k = 0; k < nsteps; ++k) {
-    if (s->cfg.dim == 2) {
+    if (s->L.q25) {
+      StepArgs a = s->args;
+      a.n_in = s->n[s->cur];
+      a.n_out = s->n[1 - s->cur];
+      a.U_in = s->U[s->cur];
+      a.U_out = s->U[1 - s->cur];
+      POND_HIP(launch_q25_step(s->L.fp64, a, s->qP, s->qfr, s->qfp[0], s->qfp[1], s->qff[0],
+                               s->qff[1], s->qps[0], s->qps[1], s->stream));
+    } else if (s->cfg.dim == 2) {
       if (s->cfg.lattice == POND_D2Q9_D2Q16) {
         // this step's f-lattices, from the state at its start
         StepArgs a = s->args;
@@ -465,6 +501,7 @@ int pond_totals(pond_state* s, double out[4]) {
 
 int pond_export_state(pond_state* s, double* f, double* g, double* frame) {
   if (!s || !s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
+  if (s->L.q25) return fail(POND_ERR_UNSUPPORTED, "export covers the D2Q16 and D2Q9 f-lattices");
   int rc = sync_flag(s);
   const size_t n = s->L.cells, chunk = s->L.stage_cells, rows = size_t(s->L.NP + 3);
   const int QF = s->L.QF, QG = s->L.QG;
@@ -491,7 +528,7 @@ int pond_lattice_map(pond_state* s, int* q, double* theta) {
   if (!s || !s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
   POND_HIP(hipStreamSynchronize(s->stream));
   const size_t n = s->L.cells;
-  const int q_all = s->cfg.dim == 2 ? 16 : 4;
+  const int q_all = s->cfg.dim == 2 ? (s->L.q25 ? 25 : 16) : 4;
   if (q) {
     if (!s->L.ms) {
       for (size_t k = 0; k < n; ++k) q[k] = q_all;

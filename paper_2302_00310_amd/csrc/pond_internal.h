@@ -21,6 +21,12 @@ constexpr double kWB = 0.04587585476806849;   // (3 - sqrt 6) / 12
 constexpr double kKA = -0.13755667699048205;  // 1 / (2A (A^2 - B^2))
 constexpr double kKB = 0.04372063527294086;   // 1 / (2B (B^2 - A^2))
 constexpr double kR3 = 1.7320508075688772;    // sqrt 3
+// D1Q5 (the 1D factor of D2Q25): nodes -B5, -A5, 0, A5, B5, weights
+// W5B, W5A, 8/15, W5A, W5B.
+constexpr double kA5 = 1.355626179974266;     // sqrt(5 - sqrt 10)
+constexpr double kB5 = 2.8569700138728056;    // sqrt(5 + sqrt 10)
+constexpr double kW5A = 0.22207592200561266;  // (7 + 2 sqrt 10) / 60
+constexpr double kW5B = 0.01125741132772069;  // (7 - 2 sqrt 10) / 60
 
 // Tile shapes of the fused step kernel.
 constexpr int kTX2 = 16, kTY2 = 15;  // 2D: 240 cells, 255 x-faces, 256 y-faces
@@ -91,6 +97,11 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
 hipError_t launch_switch(const StepArgs& a, const long long* U, double threshold, double gamma,
                          double* theta, unsigned char* lat_out, hipStream_t st);
 hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
+// One step of a D2Q25 solve (cell pass, x- and y-face passes, update),
+// a.n_in/U_in -> a.n_out/U_out, with the intermediate buffers given.
+hipError_t launch_q25_step(bool fp64, const StepArgs& a, void* P, double* fr, void* fpx, void* fpy,
+                           double* ffx, double* ffy, long long* psx, long long* psy,
+                           hipStream_t st);
 // Wall ghosts of one 2D solve from the ledger a.U_in (into a.wU, a.wN).
 hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, hipStream_t st);
 hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,

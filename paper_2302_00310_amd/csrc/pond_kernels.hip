@@ -48,7 +48,9 @@ __device__ __forceinline__ void static_for(F&& f) {
 // --------------------------------------------------------------------------
 template <int Q1, typename T>
 __device__ __forceinline__ constexpr T node(int k) {
-  if constexpr (Q1 == 4) {
+  if constexpr (Q1 == 5) {
+    return k == 0 ? T(-kB5) : k == 1 ? T(-kA5) : k == 2 ? T(0) : k == 3 ? T(kA5) : T(kB5);
+  } else if constexpr (Q1 == 4) {
     return k == 0 ? T(-kB) : k == 1 ? T(-kA) : k == 2 ? T(kA) : T(kB);
   } else {
     return k == 0 ? T(-kR3) : k == 1 ? T(0) : T(kR3);
@@ -56,7 +58,9 @@ __device__ __forceinline__ constexpr T node(int k) {
 }
 template <int Q1, typename T>
 __device__ __forceinline__ constexpr T weight(int k) {
-  if constexpr (Q1 == 4) {
+  if constexpr (Q1 == 5) {
+    return (k == 0 || k == 4) ? T(kW5B) : (k == 1 || k == 3) ? T(kW5A) : T(8.0 / 15.0);
+  } else if constexpr (Q1 == 4) {
     return (k == 0 || k == 3) ? T(kWB) : T(kWA);
   } else {
     return k == 1 ? T(2.0 / 3.0) : T(1.0 / 6.0);
@@ -219,7 +223,11 @@ __device__ __forceinline__ void transform_part(T s, T dn, T dt, const T* in, T* 
 template <int Q1>
 __host__ __device__ constexpr double hermite_node(int a, int k) {
   const double c = node<Q1, double>(k);
-  return a == 0 ? 1.0 : a == 1 ? c : a == 2 ? (c * c - 1.0) / 2.0 : (c * c * c - 3.0 * c) / 6.0;
+  return a == 0   ? 1.0
+         : a == 1 ? c
+         : a == 2 ? (c * c - 1.0) / 2.0
+         : a == 3 ? (c * c * c - 3.0 * c) / 6.0
+                  : (c * c * c * c - 6.0 * c * c + 3.0) / 24.0;
 }
 
 // Grad's expansion of order K from a source lattice with QS nodes per axis
@@ -238,19 +246,20 @@ __host__ __device__ constexpr double hermite_node(int a, int k) {
 template <int QS, int QT, int K, typename T, int AXIS>
 __device__ __forceinline__ void grad_map(T s, T dn, T dt, const T* in, T* out) {
   constexpr int SN = AXIS == 0 ? 1 : QS, ST = AXIS == 0 ? QS : 1;
-  auto herm = [](T x, T (&h)[4]) {  // He_0..He_K at x
+  auto herm = [](T x, T (&h)[5]) {  // He_0..He_K at x
     const T x2 = x * x;
     h[0] = T(1);
     h[1] = x;
     h[2] = x2 - T(1);
-    if constexpr (K == 3) h[3] = x * (x2 - T(3));
+    if constexpr (K >= 3) h[3] = x * (x2 - T(3));
+    if constexpr (K >= 4) h[4] = x2 * (x2 - T(6)) + T(3);
   };
   // beta[mn][b] = sum_mt He_b(y_mt) f[mn][mt], accumulated point by point so
   // that only one point's Hermite values are live
   T beta[QS][K + 1];
 #pragma unroll
   for (int mt = 0; mt < QS; ++mt) {
-    T h[4];
+    T h[5];
     herm(s * node<QS, T>(mt) + dt, h);
 #pragma unroll
     for (int mn = 0; mn < QS; ++mn) {
@@ -263,7 +272,7 @@ __device__ __forceinline__ void grad_map(T s, T dn, T dt, const T* in, T* out) {
   T alpha[K + 1][K + 1];
 #pragma unroll
   for (int mn = 0; mn < QS; ++mn) {
-    T h[4];
+    T h[5];
     herm(s * node<QS, T>(mn) + dn, h);
 #pragma unroll
     for (int b = 0; b <= K; ++b) {
@@ -2011,7 +2020,366 @@ __global__ void __launch_bounds__(256) totals_kernel(const long long* U, size_t 
   }
 }
 
+// --------------------------------------------------------------------------
+// D2Q25 f-lattice with the fourth-order Grad projection (Sec. III B, the
+// full invariant moment system; g stays on D2Q9 with Grad's order 2).  Three
+// plain kernels per step, with the face data in HBM: a cell pass (first QE
+// half step, phi-bar-plus, frames), a face pass per axis (face frame and
+// corrector passes, the stencil in the face frame, MUSCL, face moments, face
+// equilibrium, inversion of eq. FluxTransf, the ledger flux), and a cell
+// update (fluxes into the cell frame, DUGKS update, new frame from the
+// ledger, re-gauge, second QE half step).  Population planes: f 0..24
+// (i = i_x + 5 i_y), g 25..33.
+// --------------------------------------------------------------------------
+constexpr int kQ25 = 25, kNP25 = 34;
+
+template <typename T>
+__device__ __forceinline__ T w25(int i) {
+  return weight<5, T>(i % 5) * weight<5, T>(i / 5);
+}
+template <typename T>
+__device__ __forceinline__ T w9(int i) {
+  return weight<3, T>(i % 3) * weight<3, T>(i / 3);
+}
+
+// QE half step on D2Q25 (same form as on D2Q16: the third Hermite moments
+// relax, eq. quasi_f) and on the D2Q9 g (first moment).
+template <typename T>
+__device__ __forceinline__ void qe_half25(T* n, T* m, T kappa) {
+  T axxx = T(0), axxy = T(0), axyy = T(0), ayyy = T(0);
+#pragma unroll
+  for (int i = 0; i < kQ25; ++i) {
+    const T cx = node<5, T>(i % 5), cy = node<5, T>(i / 5);
+    axxx += n[i] * (cx * cx * cx - T(3) * cx);
+    axxy += n[i] * (cx * cx * cy - cy);
+    axyy += n[i] * (cx * cy * cy - cx);
+    ayyy += n[i] * (cy * cy * cy - T(3) * cy);
+  }
+  T agx = T(0), agy = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    agx += m[i] * node<3, T>(i % 3);
+    agy += m[i] * node<3, T>(i / 3);
+  }
+  const T k6 = kappa * T(1.0 / 6.0);
+#pragma unroll
+  for (int i = 0; i < kQ25; ++i) {
+    const T cx = node<5, T>(i % 5), cy = node<5, T>(i / 5);
+    const T c = axxx * (cx * cx * cx - T(3) * cx) + T(3) * axxy * (cx * cx * cy - cy) +
+                T(3) * axyy * (cx * cy * cy - cx) + ayyy * (cy * cy * cy - T(3) * cy);
+    n[i] += k6 * w25<T>(i) * c;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    m[i] += kappa * w9<T>(i) * (agx * node<3, T>(i % 3) + agy * node<3, T>(i / 3));
+}
+
+// f (25) and g (9) between frames by Grad's projection (orders 4 and 2).
+template <typename T>
+__device__ __forceinline__ void xform25(double rt_src, double ux_src, double uy_src, double irt_dst,
+                                        double ux_dst, double uy_dst, const T* in, T* out) {
+  const T s = T(rt_src * irt_dst);
+  const T dx = T((ux_src - ux_dst) * irt_dst), dy = T((uy_src - uy_dst) * irt_dst);
+  grad_map<5, 5, 4, T, 0>(s, dx, dy, in, out);
+  grad_map<3, 3, 2, T, 0>(s, dx, dy, in + kQ25, out + kQ25);
+}
+
+struct Q25Bufs {
+  void* P;           // kNP25 planes of phi-bar-plus per grid cell
+  double* fr;        // 3 planes: u_x, u_y, T of each grid cell
+  void* fp[2];       // face populations phi^{lambda_F}: [axis] kNP25 planes per face
+  double* ff[2];     // face frames: [axis] 3 planes
+  long long* psi[2]; // face ledger fluxes: [axis] 4 planes
+};
+
+template <typename T>
+__global__ void q25_prep_kernel(StepArgs a, Q25Bufs b) {
+  const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= a.cells) return;
+  long long U[4];
+  T n[kNP25];
+  const T* nin = static_cast<const T*>(a.n_in);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) U[q] = a.U_in[q * a.cells + k];
+#pragma unroll
+  for (int i = 0; i < kNP25; ++i) n[i] = nin[i * a.cells + k];
+  const Frame f = gauge(U, a);
+  qe_half25<T>(n, n + kQ25, T(a.kappa));
+  const T r = T(f.rho), rg = T(a.geq * f.T * f.rho), ap = T(a.a_pre);
+  T* P = static_cast<T*>(b.P);
+#pragma unroll
+  for (int i = 0; i < kQ25; ++i) P[i * a.cells + k] = r * w25<T>(i) + ap * n[i];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) P[(kQ25 + i) * a.cells + k] = rg * w9<T>(i) + ap * n[kQ25 + i];
+  b.fr[k] = f.ux;
+  b.fr[a.cells + k] = f.uy;
+  b.fr[2 * a.cells + k] = f.T;
+}
+
+// phi-bar-plus and frame of grid cell (gx, gy), which may be a ghost: the
+// boundary rules of the step kernels (x first; periodic wraps, zero gradient
+// takes the nearest cell, inflow is the comoving equilibrium of the fixed
+// state).
+template <typename T>
+__device__ __forceinline__ void q25_slot(const StepArgs& a, const Q25Bufs& b, int gx, int gy, T* P,
+                                         double* fr) {
+  int side = -1;
+  const int sx = resolve(gx, a.nx, a.bc[0], a.bc[1], &side, 0);
+  int sy = gy;
+  if (side < 0) sy = resolve(gy, a.ny, a.bc[2], a.bc[3], &side, 2);
+  if (side >= 0) {
+    long long U[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) U[q] = a.inflow[4 * side + q];
+    const Frame f = gauge(U, a);
+    const T r = T(f.rho), rg = T(a.geq * f.T * f.rho);
+#pragma unroll
+    for (int i = 0; i < kQ25; ++i) P[i] = r * w25<T>(i);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[kQ25 + i] = rg * w9<T>(i);
+    fr[0] = f.ux;
+    fr[1] = f.uy;
+    fr[2] = f.T;
+    return;
+  }
+  const size_t c = size_t(sx) + size_t(a.nx) * size_t(sy);
+  const T* Pin = static_cast<const T*>(b.P);
+#pragma unroll
+  for (int i = 0; i < kNP25; ++i) P[i] = Pin[i * a.cells + c];
+  fr[0] = b.fr[c];
+  fr[1] = b.fr[a.cells + c];
+  fr[2] = b.fr[2 * a.cells + c];
+}
+
+// One face along AXIS between cells L = (lx, ly) and R = L + e_AXIS.
+template <typename T, int LIM, int AXIS>
+__device__ __forceinline__ void q25_face(const StepArgs& a, const Q25Bufs& b, int lx, int ly,
+                                         size_t fidx, size_t nface) {
+  // stencil slots: 0 L, 1 R, 2 L-e_a, 3 R+e_a, 4 L+e_t, 5 L-e_t, 6 R+e_t, 7 R-e_t
+  const int ex = AXIS == 0 ? 1 : 0, ey = 1 - ex;
+  const int rx = lx + ex, ry = ly + ey;
+  const int tx = ey, ty = ex;  // transverse unit vector
+  const int cxs[8] = {lx, rx, lx - ex, rx + ex, lx + tx, lx - tx, rx + tx, rx - tx};
+  const int cys[8] = {ly, ry, ly - ey, ry + ey, ly + ty, ly - ty, ry + ty, ry - ty};
+  double frs[8][3];
+  T P[8][kNP25];
+  {
+    T tmp[kNP25];
+    q25_slot<T>(a, b, cxs[0], cys[0], tmp, frs[0]);
+    q25_slot<T>(a, b, cxs[1], cys[1], tmp, frs[1]);
+  }
+  double uF = 0.5 * (frs[0][0] + frs[1][0]), vF = 0.5 * (frs[0][1] + frs[1][1]);
+  double TF = 0.5 * (frs[0][2] + frs[1][2]);
+  const T lam = T(a.lam);
+  T bar[kNP25];
+  double rho_b = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0;
+  for (int pass = 0; pass <= a.n_corr; ++pass) {
+    const double rtF = sqrt(TF), irtF = 1.0 / rtF;
+    // the stencil's phi-bar-plus in the face frame
+    for (int k = 0; k < 8; ++k) {
+      T src[kNP25];
+      q25_slot<T>(a, b, cxs[k], cys[k], src, frs[k]);
+      xform25<T>(sqrt(frs[k][2]), frs[k][0], frs[k][1], irtF, uF, vF, src, P[k]);
+    }
+    const T rt = T(rtF), band = T(kTieBand * rtF);
+#pragma unroll
+    for (int p = 0; p < kNP25; ++p) {
+      const bool f = p < kQ25;
+      const int q = f ? p : p - kQ25;
+      const T cx = f ? node<5, T>(q % 5) : node<3, T>(q % 3);
+      const T cy = f ? node<5, T>(q / 5) : node<3, T>(q / 3);
+      const T vx = rt * cx + T(uF), vy = rt * cy + T(vF);
+      const T vn = AXIS == 0 ? vx : vy, vt = AXIS == 0 ? vy : vx;
+      const T dtv = T(-0.5) * lam * vt;
+      const T recL = P[0][p] + (T(0.5) - T(0.5) * lam * vn) * limit<LIM, T>(P[0][p] - P[2][p], P[1][p] - P[0][p]) +
+                     dtv * limit<LIM, T>(P[0][p] - P[5][p], P[4][p] - P[0][p]);
+      const T recR = P[1][p] + (T(-0.5) - T(0.5) * lam * vn) * limit<LIM, T>(P[1][p] - P[0][p], P[3][p] - P[1][p]) +
+                     dtv * limit<LIM, T>(P[1][p] - P[7][p], P[6][p] - P[1][p]);
+      bar[p] = vn > band ? recL : (vn < -band ? recR : T(0.5) * (recL + recR));
+    }
+    // face moments in FP64 (eq. ConservationLaws in lambda_F)
+    double m0 = 0.0, mx = 0.0, my = 0.0, e = 0.0;
+#pragma unroll
+    for (int p = 0; p < kQ25; ++p) {
+      const double vx = rtF * node<5, double>(p % 5) + uF, vy = rtF * node<5, double>(p / 5) + vF;
+      const double fb = double(bar[p]);
+      m0 += fb;
+      mx += vx * fb;
+      my += vy * fb;
+      e += 0.5 * (vx * vx + vy * vy) * fb;
+    }
+#pragma unroll
+    for (int p = 0; p < 9; ++p) e += double(bar[kQ25 + p]);
+    rho_b = m0;
+    ub = mx / m0;
+    vb = my / m0;
+    Tb = (e - 0.5 * m0 * (ub * ub + vb * vb)) / (a.cv * m0);
+    if (pass < a.n_corr) {
+      uF = ub;
+      vF = vb;
+      TF = Tb;
+    }
+  }
+  raise_flag(a.flag, !(rho_b > 0.0) || !(Tb > 0.0), 1);
+  // face equilibrium rho_b G W (eq. NonComovingEq): the comoving equilibrium
+  // of (u_b, T_b) projected into lambda_F
+  T eqc[kNP25], eq[kNP25];
+  const T rb = T(rho_b), rgb = T(a.geq * Tb * rho_b);
+#pragma unroll
+  for (int p = 0; p < kQ25; ++p) eqc[p] = rb * w25<T>(p);
+#pragma unroll
+  for (int p = 0; p < 9; ++p) eqc[kQ25 + p] = rgb * w9<T>(p);
+  const double irtF = 1.0 / sqrt(TF);
+  xform25<T>(sqrt(Tb), ub, vb, irtF, uF, vF, eqc, eq);
+  // inversion of eq. FluxTransf and the conserved flux
+  const T c1 = T(a.c_face1), c2 = T(a.c_face2);
+  T* fp = static_cast<T*>(b.fp[AXIS]);
+  const double rtF = sqrt(TF);
+  double F0 = 0.0, Fx = 0.0, Fy = 0.0, FE = 0.0;
+#pragma unroll
+  for (int p = 0; p < kNP25; ++p) {
+    const T phi = c1 * bar[p] + c2 * eq[p];
+    fp[p * nface + fidx] = phi;
+    const double ph = double(phi);
+    if (p < kQ25) {
+      const double vx = rtF * node<5, double>(p % 5) + uF, vy = rtF * node<5, double>(p / 5) + vF;
+      const double vn = AXIS == 0 ? vx : vy;
+      F0 += vn * ph;
+      Fx += vn * vx * ph;
+      Fy += vn * vy * ph;
+      FE += vn * 0.5 * (vx * vx + vy * vy) * ph;
+    } else {
+      const int q = p - kQ25;
+      const double vn = AXIS == 0 ? rtF * node<3, double>(q % 3) + uF : rtF * node<3, double>(q / 3) + vF;
+      FE += vn * ph;
+    }
+  }
+  b.ff[AXIS][fidx] = uF;
+  b.ff[AXIS][nface + fidx] = vF;
+  b.ff[AXIS][2 * nface + fidx] = TF;
+  int bad = 0;
+  long long* psi = b.psi[AXIS];
+  psi[fidx] = to_fixed(a.lam * F0, a.scale, &bad);
+  psi[nface + fidx] = to_fixed(a.lam * Fx, a.scale, &bad);
+  psi[2 * nface + fidx] = to_fixed(a.lam * Fy, a.scale, &bad);
+  psi[3 * nface + fidx] = to_fixed(a.lam * FE, a.scale, &bad);
+  raise_flag(a.flag, bad != 0, 2);
+}
+
+template <typename T, int AXIS>
+__global__ void q25_face_kernel(StepArgs a, Q25Bufs b) {
+  // x-faces: (nx + 1) per row; y-faces: nx per row, ny + 1 rows
+  const size_t nface = AXIS == 0 ? size_t(a.nx + 1) * a.ny : size_t(a.nx) * (a.ny + 1);
+  const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= nface) return;
+  const int w = AXIS == 0 ? a.nx + 1 : a.nx;
+  const int i = int(k % size_t(w)), j = int(k / size_t(w));
+  // x-face i of row j lies between cells (i-1, j) and (i, j); y-face j of
+  // column i between (i, j-1) and (i, j)
+  const int lx = AXIS == 0 ? i - 1 : i, ly = AXIS == 0 ? j : j - 1;
+  if (a.limiter == LIM_MINMOD) q25_face<T, LIM_MINMOD, AXIS>(a, b, lx, ly, k, nface);
+  else q25_face<T, LIM_VANLEER, AXIS>(a, b, lx, ly, k, nface);
+}
+
+template <typename T>
+__global__ void q25_cell_kernel(StepArgs a, Q25Bufs b) {
+  const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= a.cells) return;
+  const int x = int(k % size_t(a.nx)), y = int(k / size_t(a.nx));
+  long long U[4];
+  T n[kNP25];
+  const T* nin = static_cast<const T*>(a.n_in);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) U[q] = a.U_in[q * a.cells + k];
+#pragma unroll
+  for (int i = 0; i < kNP25; ++i) n[i] = nin[i * a.cells + k];
+  const Frame f0 = gauge(U, a);
+  qe_half25<T>(n, n + kQ25, T(a.kappa));
+  // faces: west, east (x-faces), south, north (y-faces), sign -1 / +1
+  const size_t nfx = size_t(a.nx + 1) * a.ny, nfy = size_t(a.nx) * (a.ny + 1);
+  const size_t fi[4] = {size_t(x) + size_t(a.nx + 1) * y, size_t(x + 1) + size_t(a.nx + 1) * y,
+                        size_t(x) + size_t(a.nx) * y, size_t(x) + size_t(a.nx) * (y + 1)};
+  T acc[kNP25];
+#pragma unroll
+  for (int p = 0; p < kNP25; ++p) acc[p] = T(0);
+  long long dU[4] = {0, 0, 0, 0};
+  const T rt0 = T(f0.rt);
+#pragma unroll
+  for (int fc = 0; fc < 4; ++fc) {
+    const int ax = fc / 2;
+    const size_t nf = ax == 0 ? nfx : nfy, id = fi[fc];
+    const T* fp = static_cast<const T*>(b.fp[ax]);
+    T in[kNP25], out[kNP25];
+#pragma unroll
+    for (int p = 0; p < kNP25; ++p) in[p] = fp[p * nf + id];
+    const double uF = b.ff[ax][id], vF = b.ff[ax][nf + id], TF = b.ff[ax][2 * nf + id];
+    xform25<T>(sqrt(TF), uF, vF, f0.irt, f0.ux, f0.uy, in, out);
+    const T sg = fc % 2 == 0 ? T(-1) : T(1);
+    const T u0 = T(ax == 0 ? f0.ux : f0.uy);
+#pragma unroll
+    for (int p = 0; p < kNP25; ++p) {
+      const T c = p < kQ25 ? (ax == 0 ? node<5, T>(p % 5) : node<5, T>(p / 5))
+                           : (ax == 0 ? node<3, T>((p - kQ25) % 3) : node<3, T>((p - kQ25) / 3));
+      acc[p] += sg * (rt0 * c + u0) * out[p];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dU[q] += fc % 2 == 0 ? -b.psi[ax][q * nf + id] : b.psi[ax][q * nf + id];
+  }
+  // DUGKS update (eq. FinalUpdateDUGKS) in the cell frame
+  const T bu = T(a.b_upd), lam = T(a.lam);
+  const T r = T(f0.rho), rg = T(a.geq * f0.T * f0.rho);
+  T ft[kNP25];
+#pragma unroll
+  for (int p = 0; p < kQ25; ++p) ft[p] = r * w25<T>(p) + bu * n[p] - lam * acc[p];
+#pragma unroll
+  for (int p = 0; p < 9; ++p) ft[kQ25 + p] = rg * w9<T>(p) + bu * n[kQ25 + p] - lam * acc[kQ25 + p];
+  long long U2[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) U2[q] = U[q] - dU[q];
+  const Frame nf = gauge(U2, a);
+  T n2[kNP25];
+  xform25<T>(f0.rt, f0.ux, f0.uy, nf.irt, nf.ux, nf.uy, ft, n2);
+  const T r2 = T(nf.rho), rg2 = T(a.geq * nf.T * nf.rho);
+#pragma unroll
+  for (int p = 0; p < kQ25; ++p) n2[p] -= r2 * w25<T>(p);
+#pragma unroll
+  for (int p = 0; p < 9; ++p) n2[kQ25 + p] -= rg2 * w9<T>(p);
+  qe_half25<T>(n2, n2 + kQ25, T(a.kappa));
+  raise_flag(a.flag, !(nf.rho > 0.0) || !(nf.T > 0.0) || !isfinite(double(n2[0])), 1);
+  bool over = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) over |= (U2[q] > (1LL << 62)) || (U2[q] < -(1LL << 62));
+  raise_flag(a.flag, over, 2);
+  T* nout = static_cast<T*>(a.n_out);
+#pragma unroll
+  for (int p = 0; p < kNP25; ++p) nout[p * a.cells + k] = n2[p];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) a.U_out[q * a.cells + k] = U2[q];
+}
+
 }  // namespace
+
+hipError_t launch_q25_step(bool fp64, const StepArgs& a, void* P, double* fr, void* fpx, void* fpy,
+                           double* ffx, double* ffy, long long* psx, long long* psy,
+                           hipStream_t st) {
+  Q25Bufs b{P, fr, {fpx, fpy}, {ffx, ffy}, {psx, psy}};
+  const dim3 block(256);
+  const dim3 gc(unsigned((a.cells + 255) / 256));
+  const dim3 gx(unsigned((size_t(a.nx + 1) * a.ny + 255) / 256));
+  const dim3 gy(unsigned((size_t(a.nx) * (a.ny + 1) + 255) / 256));
+  if (fp64) {
+    hipLaunchKernelGGL(q25_prep_kernel<double>, gc, block, 0, st, a, b);
+    hipLaunchKernelGGL((q25_face_kernel<double, 0>), gx, block, 0, st, a, b);
+    hipLaunchKernelGGL((q25_face_kernel<double, 1>), gy, block, 0, st, a, b);
+    hipLaunchKernelGGL(q25_cell_kernel<double>, gc, block, 0, st, a, b);
+  } else {
+    hipLaunchKernelGGL(q25_prep_kernel<float>, gc, block, 0, st, a, b);
+    hipLaunchKernelGGL((q25_face_kernel<float, 0>), gx, block, 0, st, a, b);
+    hipLaunchKernelGGL((q25_face_kernel<float, 1>), gy, block, 0, st, a, b);
+    hipLaunchKernelGGL(q25_cell_kernel<float>, gc, block, 0, st, a, b);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st) {
   const dim3 grid(a.tiles_x * a.tiles_y), block(kThreads);

@@ -24,6 +24,8 @@ struct Layout {
   bool ms = false;                 // per-cell f-lattices (D2Q9 or multiscale)
   size_t lat_bytes = 0, theta_bytes = 0;
   size_t wall_len = 0, wall_bytes = 0;  // wall ghost entries per side and layer; their bytes
+  bool q25 = false;                // D2Q25 f-lattice: unfused kernels with HBM face data
+  size_t q25_P = 0, q25_fr = 0, q25_nfx = 0, q25_nfy = 0, q25_bytes = 0;
   size_t total = 0;
 };
 
@@ -50,6 +52,13 @@ struct pond_state {
   double* theta = nullptr;                     // multiscale switch indicator
   long long* wU = nullptr;                     // wall ghosts: 4 ledger planes of 8 wall_len entries
   void* wN = nullptr;                          // wall ghosts: NP population planes
+  // D2Q25 intermediates: phi-bar-plus and frames per cell; per x- and y-face
+  // the face populations, frames and ledger fluxes
+  void* qP = nullptr;
+  double* qfr = nullptr;
+  void* qfp[2] = {nullptr, nullptr};
+  double* qff[2] = {nullptr, nullptr};
+  long long* qps[2] = {nullptr, nullptr};
   int cur = 0;
   int64_t nstep = 0;
   bool initialized = false;

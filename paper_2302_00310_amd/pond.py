@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpond.so")
 POND_OK, POND_PENDING = 0, 1
 ERRORS = {-1: "POND_ERR_INVALID", -2: "POND_ERR_NOMEM", -3: "POND_ERR_DEVICE",
           -4: "POND_ERR_UNSTABLE", -5: "POND_ERR_REJECTED", -6: "POND_ERR_UNSUPPORTED"}
-POND_D1Q4, POND_D2Q16, POND_D2Q9, POND_D2Q9_D2Q16 = 1, 2, 3, 4
+POND_D1Q4, POND_D2Q16, POND_D2Q9, POND_D2Q9_D2Q16, POND_D2Q25 = 1, 2, 3, 4, 5
 POND_FP64, POND_MIXED = 0, 1
 POND_TF_LAGRANGE, POND_TF_GRAD = 0, 1
 POND_BC_PERIODIC, POND_BC_ZERO_GRADIENT, POND_BC_INFLOW, POND_BC_WALL = 0, 1, 2, 3

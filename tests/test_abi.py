@@ -154,3 +154,16 @@ def test_body_force_config_rules(pond):
     c = pond.make_config(wl)
     c.accel[1] = float("inf")
     assert pond.pond_state_bytes(c) == 0
+
+
+def test_d2q25_config_rules(pond):
+    """D2Q25 needs Grad's projection and 2D; its footprint holds 34
+    population planes per cell and the face buffers."""
+    assert pond.pond_state_bytes(_cfg(pond, lattice=5, transform=0)) == 0
+    q16 = pond.pond_state_bytes(_cfg(pond, transform=1))
+    q25 = pond.pond_state_bytes(_cfg(pond, lattice=5, transform=1))
+    assert q25 >= q16 + 2 * 9 * 4 * 32 * 32 + 2 * 33 * 32 * 34 * 4
+    wl = inputs.thermal_couette_2d(ny=32, nx=40)
+    c = pond.make_config(wl, transform=1, lattice=5)
+    h = C.c_void_p()
+    assert pond.load_library().pond_create(C.byref(c), None, 0, None, C.byref(h)) == -6
