@@ -38,10 +38,10 @@ BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
 KERNEL_SOURCES = ("paper_2302_00310_amd/csrc/pond_kernels.hip",
                   "paper_2302_00310_amd/csrc/pond_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "fc2cacd4f77a11645b3ab735e05cd2344639018ffc4bdf1dc51f32302290a568",
+    "sha256": "ba6c53688ff6d0dd4fa71243b9de9b304f725f42c25b6003820c5a40dd99f024",
     "n": 2048,
-    "fetch_bytes": 1.65020e+09,
-    "write_bytes": 7.85312e+08,
+    "fetch_bytes": 1.66498e+09,
+    "write_bytes": 7.87696e+08,
 }
 
 
@@ -96,6 +96,7 @@ def parse():
                    help="skip the multiscale D2Q9/D2Q16 leg")
     p.add_argument("--no-walls", action="store_true", help="skip the wall-boundary leg")
     p.add_argument("--no-force", action="store_true", help="skip the body-force leg")
+    p.add_argument("--no-d2q25", action="store_true", help="skip the D2Q25 leg")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--serving-requests", type=int, default=64,
                    help="requests of the serving leg (0 skips it)")
@@ -292,6 +293,24 @@ def force_leg(n, steps, warmup):
     return out
 
 
+def d2q25_leg(n, steps, warmup):
+    """The D2Q25 f-lattice with the fourth-order Grad projection (three plain
+    kernels per step with the face data in HBM) against the fused D2Q16 step
+    with Grad's projection, on the four-quadrant workload n^2, mixed and
+    FP64."""
+    from paper_2302_00310_amd import inputs, pond
+    wl = inputs.quadrants_2d(n, steps=steps)
+    cells = n * n
+    out = {"workload": f"four-quadrant 2D Riemann stand-in {n}x{n} (seed 3), Grad's projection"}
+    for name, prec, lat in (("d2q25_mixed", pond.POND_MIXED, pond.POND_D2Q25),
+                            ("d2q25_fp64", pond.POND_FP64, pond.POND_D2Q25),
+                            ("d2q16_mixed", pond.POND_MIXED, pond.POND_D2Q16)):
+        wall, kern = time_path(wl, prec, steps, warmup, transform=pond.POND_TF_GRAD, lattice=lat)
+        out[name] = {"value": cells * steps / wall, "unit": "cell-updates/s", "ms_per_step": kern}
+    out["d2q25_over_d2q16_mixed"] = out["d2q25_mixed"]["value"] / out["d2q16_mixed"]["value"]
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -339,6 +358,8 @@ def main():
         out["walls"] = walls_leg(a.n, max(1, a.steps // 2), a.warmup)
     if not a.no_force:
         out["force"] = force_leg(a.n, max(1, a.steps // 2), a.warmup)
+    if not a.no_d2q25:
+        out["d2q25"] = d2q25_leg(a.n, max(1, a.steps // 10), 2)
     if a.serving_requests > 0:
         sizes = tuple(int(v) for v in a.serving_sizes.split(","))
         out["serving"] = serving_leg(a.serving_requests, sizes, a.serving_arena_gb,
