@@ -2092,8 +2092,11 @@ struct Q25Bufs {
   long long* psi[2]; // face ledger fluxes: [axis] 4 planes
 };
 
+// 256-thread blocks: without the bound the compiler keeps each thread to 128
+// VGPRs (room for 1024-thread blocks) and the face and cell passes, which
+// hold eight projected stencil cells or four face sets, spill to scratch.
 template <typename T>
-__global__ void q25_prep_kernel(StepArgs a, Q25Bufs b) {
+__global__ void __launch_bounds__(256) q25_prep_kernel(StepArgs a, Q25Bufs b) {
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= a.cells) return;
   long long U[4];
@@ -2175,11 +2178,20 @@ __device__ __forceinline__ void q25_face(const StepArgs& a, const Q25Bufs& b, in
   double rho_b = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0;
   for (int pass = 0; pass <= a.n_corr; ++pass) {
     const double rtF = sqrt(TF), irtF = 1.0 / rtF;
-    // the stencil's phi-bar-plus in the face frame
-    for (int k = 0; k < 8; ++k) {
+    // the stencil's phi-bar-plus in the face frame.  FP32: unrolled, so that
+    // P stays in registers (constant indices); FP64: P does not fit them
+    // and a rolled loop keeps the rest of the pass in registers
+    auto slot = [&](int k) {
       T src[kNP25];
       q25_slot<T>(a, b, cxs[k], cys[k], src, frs[k]);
       xform25<T>(sqrt(frs[k][2]), frs[k][0], frs[k][1], irtF, uF, vF, src, P[k]);
+    };
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) slot(k);
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k) slot(k);
     }
     const T rt = T(rtF), band = T(kTieBand * rtF);
 #pragma unroll
@@ -2267,7 +2279,7 @@ __device__ __forceinline__ void q25_face(const StepArgs& a, const Q25Bufs& b, in
 }
 
 template <typename T, int AXIS>
-__global__ void q25_face_kernel(StepArgs a, Q25Bufs b) {
+__global__ void __launch_bounds__(256) q25_face_kernel(StepArgs a, Q25Bufs b) {
   // x-faces: (nx + 1) per row; y-faces: nx per row, ny + 1 rows
   const size_t nface = AXIS == 0 ? size_t(a.nx + 1) * a.ny : size_t(a.nx) * (a.ny + 1);
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -2282,7 +2294,7 @@ __global__ void q25_face_kernel(StepArgs a, Q25Bufs b) {
 }
 
 template <typename T>
-__global__ void q25_cell_kernel(StepArgs a, Q25Bufs b) {
+__global__ void __launch_bounds__(256) q25_cell_kernel(StepArgs a, Q25Bufs b) {
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= a.cells) return;
   const int x = int(k % size_t(a.nx)), y = int(k / size_t(a.nx));
