@@ -38,10 +38,10 @@ BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
 KERNEL_SOURCES = ("paper_2302_00310_amd/csrc/pond_kernels.hip",
                   "paper_2302_00310_amd/csrc/pond_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "ba6c53688ff6d0dd4fa71243b9de9b304f725f42c25b6003820c5a40dd99f024",
+    "sha256": "c1d0d50992bd4cd1e896ab6173ea91c1809954d55c0b3771b4e8049d4c282c34",
     "n": 2048,
-    "fetch_bytes": 1.66498e+09,
-    "write_bytes": 7.87696e+08,
+    "fetch_bytes": 1.65066e+09,
+    "write_bytes": 7.81024e+08,
 }
 
 

@@ -622,6 +622,11 @@ int pond_load(pond_state* s, const char* path) {
   s->args.scale = s->scale;
   s->args.inv_scale = std::ldexp(1.0, -h.scale_bits);
   s->args.lam = s->dt / s->dx;
+  // the arguments that scale with dt (body force, wall relaxation times)
+  s->args.hax = 0.5 * s->dt * s->cfg.accel[0];
+  s->args.hay = 0.5 * s->dt * s->cfg.accel[1];
+  s->args.tau1 = s->cfg.tau * s->dt;
+  s->args.tau2 = s->cfg.tau * s->dt / s->cfg.prandtl;
   for (int k = 0; k < 4; ++k) {
     const double* st = s->cfg.inflow[k];
     double U4[4];

@@ -133,3 +133,21 @@ def test_d2q25_full_size_sampled_cells(pond):
         got = np.array([[float(a[y, x]) for a in m] for (x, y) in pts])
         e = moment_errors(tuple(got.T), tuple(ref.T), l2=(precision == MIXED))
         assert max(e.values()) <= (1e-12 if precision == FP64 else 1e-5), (precision, e)
+
+
+def test_d2q25_checkpoint_resume_bitwise(pond, tmp_path):
+    wl = CASES["shu_osher_48x20"]()
+    a = pond.Solver(wl, precision=FP64, transform=GRAD, lattice=Q25)
+    b = pond.Solver(wl, precision=FP64, transform=GRAD, lattice=Q25, init=False)
+    try:
+        a.step(5)
+        path = str(tmp_path / "q25.ckpt")
+        pond.pond_save(a.h, path)
+        pond.pond_load(b.h, path)
+        a.step(6)
+        b.step(6)
+        for x, y in zip(a.moments(), b.moments()):
+            assert np.array_equal(x, y)
+    finally:
+        a.close()
+        b.close()
