@@ -281,6 +281,16 @@ __device__ __forceinline__ void grad_map(T s, T dn, T dt, const T* in, T* out) {
         alpha[a][b] = mn == 0 ? h[a] * beta[0][b] : alpha[a][b] + h[a] * beta[mn][b];
     }
   }
+  // FP32: the Hermite moments are finished before the expansion starts (the
+  // empty asm keeps the compiler from interleaving the two stages, which
+  // left more values live than the registers hold and spilled)
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int b = 0; b <= K; ++b) {
+#pragma unroll
+      for (int a = 0; a + b <= K; ++a) asm volatile("" : "+v"(alpha[a][b]));
+    }
+  }
   // gamma[kn][b] = W_kn sum_{a <= K - b} He_a(c_kn)/a! alpha[a][b];
   // out[kn][kt] = W_kt sum_b He_b(c_kt)/b! gamma[kn][b]
 #pragma unroll
