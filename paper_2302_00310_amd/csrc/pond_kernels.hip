@@ -2129,11 +2129,11 @@ __global__ void __launch_bounds__(256) q25_prep_kernel(StepArgs a, Q25Bufs b) {
   b.fr[2 * a.cells + k] = f.T;
 }
 
-// phi-bar-plus and frame of grid cell (gx, gy), which may be a ghost: the
-// boundary rules of the step kernels (x first; periodic wraps, zero gradient
-// takes the nearest cell, inflow is the comoving equilibrium of the fixed
-// state).
-template <typename T>
+// phi-bar-plus planes [P0, P0 + NQ) and frame of grid cell (gx, gy), which
+// may be a ghost: the boundary rules of the step kernels (x first; periodic
+// wraps, zero gradient takes the nearest cell, inflow is the comoving
+// equilibrium of the fixed state).
+template <typename T, int P0, int NQ>
 __device__ __forceinline__ void q25_slot(const StepArgs& a, const Q25Bufs& b, int gx, int gy, T* P,
                                          double* fr) {
   int side = -1;
@@ -2145,11 +2145,9 @@ __device__ __forceinline__ void q25_slot(const StepArgs& a, const Q25Bufs& b, in
 #pragma unroll
     for (int q = 0; q < 4; ++q) U[q] = a.inflow[4 * side + q];
     const Frame f = gauge(U, a);
-    const T r = T(f.rho), rg = T(a.geq * f.T * f.rho);
+    const T r = P0 == 0 ? T(f.rho) : T(a.geq * f.T * f.rho);
 #pragma unroll
-    for (int i = 0; i < kQ25; ++i) P[i] = r * w25<T>(i);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) P[kQ25 + i] = rg * w9<T>(i);
+    for (int i = 0; i < NQ; ++i) P[i] = r * (P0 == 0 ? w25<T>(i) : w9<T>(i));
     fr[0] = f.ux;
     fr[1] = f.uy;
     fr[2] = f.T;
@@ -2158,10 +2156,51 @@ __device__ __forceinline__ void q25_slot(const StepArgs& a, const Q25Bufs& b, in
   const size_t c = size_t(sx) + size_t(a.nx) * size_t(sy);
   const T* Pin = static_cast<const T*>(b.P);
 #pragma unroll
-  for (int i = 0; i < kNP25; ++i) P[i] = Pin[i * a.cells + c];
+  for (int i = 0; i < NQ; ++i) P[i] = Pin[(P0 + i) * a.cells + c];
   fr[0] = b.fr[c];
   fr[1] = b.fr[a.cells + c];
   fr[2] = b.fr[2 * a.cells + c];
+}
+
+// The face reconstruction of one lattice: f (Q1 = 5, planes 0..24) or g
+// (Q1 = 3, planes 25..33).  The eight stencil cells are projected into the
+// face frame by Grad's expansion of order Q1 - 1 and kept in registers
+// through the MUSCL step; doing the lattices one after the other halves the
+// values held at once.
+template <typename T, int LIM, int AXIS, int Q1, int P0>
+__device__ __forceinline__ void q25_part(const StepArgs& a, const Q25Bufs& b, const int (&cxs)[8],
+                                         const int (&cys)[8], double uF, double vF, double TF,
+                                         T* bar) {
+  constexpr int NQ = Q1 * Q1;
+  const double rtF = sqrt(TF), irtF = 1.0 / rtF;
+  T P[8][NQ];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    T src[NQ];
+    double fr[3];
+    q25_slot<T, P0, NQ>(a, b, cxs[k], cys[k], src, fr);
+    const T s = T(sqrt(fr[2]) * irtF);
+    const T dx = T((fr[0] - uF) * irtF), dy = T((fr[1] - vF) * irtF);
+    grad_map<Q1, Q1, Q1 - 1, T, 0>(s, dx, dy, src, P[k]);
+    // one stencil cell at a time: its projection finished and pinned before
+    // the next cell's loads (the compiler would otherwise hoist all loads
+    // and hold them with the results)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(P[k][i]));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const T rt = T(rtF), band = T(kTieBand * rtF), lam = T(a.lam);
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) {
+    const T vx = rt * node<Q1, T>(p % Q1) + T(uF), vy = rt * node<Q1, T>(p / Q1) + T(vF);
+    const T vn = AXIS == 0 ? vx : vy, vt = AXIS == 0 ? vy : vx;
+    const T dtv = T(-0.5) * lam * vt;
+    const T recL = P[0][p] + (T(0.5) - T(0.5) * lam * vn) * limit<LIM, T>(P[0][p] - P[2][p], P[1][p] - P[0][p]) +
+                   dtv * limit<LIM, T>(P[0][p] - P[5][p], P[4][p] - P[0][p]);
+    const T recR = P[1][p] + (T(-0.5) - T(0.5) * lam * vn) * limit<LIM, T>(P[1][p] - P[0][p], P[3][p] - P[1][p]) +
+                   dtv * limit<LIM, T>(P[1][p] - P[7][p], P[6][p] - P[1][p]);
+    bar[P0 + p] = vn > band ? recL : (vn < -band ? recR : T(0.5) * (recL + recR));
+  }
 }
 
 // One face along AXIS between cells L = (lx, ly) and R = L + e_AXIS.
@@ -2174,51 +2213,20 @@ __device__ __forceinline__ void q25_face(const StepArgs& a, const Q25Bufs& b, in
   const int tx = ey, ty = ex;  // transverse unit vector
   const int cxs[8] = {lx, rx, lx - ex, rx + ex, lx + tx, lx - tx, rx + tx, rx - tx};
   const int cys[8] = {ly, ry, ly - ey, ry + ey, ly + ty, ly - ty, ry + ty, ry - ty};
-  double frs[8][3];
-  T P[8][kNP25];
+  double frL[3], frR[3];
   {
-    T tmp[kNP25];
-    q25_slot<T>(a, b, cxs[0], cys[0], tmp, frs[0]);
-    q25_slot<T>(a, b, cxs[1], cys[1], tmp, frs[1]);
+    T tmp[9];
+    q25_slot<T, kQ25, 9>(a, b, cxs[0], cys[0], tmp, frL);
+    q25_slot<T, kQ25, 9>(a, b, cxs[1], cys[1], tmp, frR);
   }
-  double uF = 0.5 * (frs[0][0] + frs[1][0]), vF = 0.5 * (frs[0][1] + frs[1][1]);
-  double TF = 0.5 * (frs[0][2] + frs[1][2]);
-  const T lam = T(a.lam);
+  double uF = 0.5 * (frL[0] + frR[0]), vF = 0.5 * (frL[1] + frR[1]);
+  double TF = 0.5 * (frL[2] + frR[2]);
   T bar[kNP25];
   double rho_b = 0.0, ub = 0.0, vb = 0.0, Tb = 0.0;
   for (int pass = 0; pass <= a.n_corr; ++pass) {
-    const double rtF = sqrt(TF), irtF = 1.0 / rtF;
-    // the stencil's phi-bar-plus in the face frame.  FP32: unrolled, so that
-    // P stays in registers (constant indices); FP64: P does not fit them
-    // and a rolled loop keeps the rest of the pass in registers
-    auto slot = [&](int k) {
-      T src[kNP25];
-      q25_slot<T>(a, b, cxs[k], cys[k], src, frs[k]);
-      xform25<T>(sqrt(frs[k][2]), frs[k][0], frs[k][1], irtF, uF, vF, src, P[k]);
-    };
-    if constexpr (sizeof(T) == 4) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) slot(k);
-    } else {
-#pragma unroll 1
-      for (int k = 0; k < 8; ++k) slot(k);
-    }
-    const T rt = T(rtF), band = T(kTieBand * rtF);
-#pragma unroll
-    for (int p = 0; p < kNP25; ++p) {
-      const bool f = p < kQ25;
-      const int q = f ? p : p - kQ25;
-      const T cx = f ? node<5, T>(q % 5) : node<3, T>(q % 3);
-      const T cy = f ? node<5, T>(q / 5) : node<3, T>(q / 3);
-      const T vx = rt * cx + T(uF), vy = rt * cy + T(vF);
-      const T vn = AXIS == 0 ? vx : vy, vt = AXIS == 0 ? vy : vx;
-      const T dtv = T(-0.5) * lam * vt;
-      const T recL = P[0][p] + (T(0.5) - T(0.5) * lam * vn) * limit<LIM, T>(P[0][p] - P[2][p], P[1][p] - P[0][p]) +
-                     dtv * limit<LIM, T>(P[0][p] - P[5][p], P[4][p] - P[0][p]);
-      const T recR = P[1][p] + (T(-0.5) - T(0.5) * lam * vn) * limit<LIM, T>(P[1][p] - P[0][p], P[3][p] - P[1][p]) +
-                     dtv * limit<LIM, T>(P[1][p] - P[7][p], P[6][p] - P[1][p]);
-      bar[p] = vn > band ? recL : (vn < -band ? recR : T(0.5) * (recL + recR));
-    }
+    const double rtF = sqrt(TF);
+    q25_part<T, LIM, AXIS, 5, 0>(a, b, cxs, cys, uF, vF, TF, bar);
+    q25_part<T, LIM, AXIS, 3, kQ25>(a, b, cxs, cys, uF, vF, TF, bar);
     // face moments in FP64 (eq. ConservationLaws in lambda_F)
     double m0 = 0.0, mx = 0.0, my = 0.0, e = 0.0;
 #pragma unroll
@@ -2289,7 +2297,7 @@ __device__ __forceinline__ void q25_face(const StepArgs& a, const Q25Bufs& b, in
 }
 
 template <typename T, int AXIS>
-__global__ void __launch_bounds__(256) q25_face_kernel(StepArgs a, Q25Bufs b) {
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) q25_face_kernel(StepArgs a, Q25Bufs b) {
   // x-faces: (nx + 1) per row; y-faces: nx per row, ny + 1 rows
   const size_t nface = AXIS == 0 ? size_t(a.nx + 1) * a.ny : size_t(a.nx) * (a.ny + 1);
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
