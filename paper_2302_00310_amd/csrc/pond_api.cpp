@@ -421,7 +421,7 @@ int pond_step(pond_state* s, int nsteps) {
         // wall ghosts from the state at the start of this step
         StepArgs a = s->args;
         a.U_in = s->U[s->cur];
-        POND_HIP(launch_wall_ghosts(s->L.fp64, a, s->stream));
+        POND_HIP(launch_wall_ghosts(s->L.fp64, a, s->wU, s->wN, s->stream));
       }
       POND_HIP(launch_step_batch(s->L.fp64, 1u << kind_of(s->cfg.transform, s->args.ms), s->tab, 1,
                                  s->args.tiles_x * s->args.tiles_y, s->cur, s->stream));

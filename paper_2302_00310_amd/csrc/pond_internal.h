@@ -102,8 +102,10 @@ hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
 hipError_t launch_q25_step(bool fp64, const StepArgs& a, void* P, double* fr, void* fpx, void* fpy,
                            double* ffx, double* ffy, long long* psx, long long* psy,
                            hipStream_t st);
-// Wall ghosts of one 2D solve from the ledger a.U_in (into a.wU, a.wN).
-hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, hipStream_t st);
+// Wall ghosts of one 2D solve from the ledger a.U_in, written to wU / wN
+// (the buffers a.wU / a.wN point to).
+hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, long long* wU, void* wN,
+                              hipStream_t st);
 hipError_t launch_init(int dim, bool fp64, const double* fields, size_t cells, size_t first,
                        size_t count, double scale, double cv, void* n, long long* U,
                        hipStream_t st);

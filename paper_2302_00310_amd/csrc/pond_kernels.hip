@@ -1872,7 +1872,9 @@ __device__ __forceinline__ Prim wall_field(const StepArgs& a, int side, int m, i
   long long u[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) u[q] = a.U_in[q * a.cells + cell];
-  // the ghosts follow the cells after the first body-force half step
+  // the ghosts follow the cells after the first body-force half step (an
+  // overflow of these increments is flagged where the step kernel applies
+  // the same ones to the cell)
   int bad = 0;
   if (a.force) force_ledger(a, u, &bad);
   const Frame f = gauge(u, a);
@@ -1885,8 +1887,10 @@ __device__ __forceinline__ Prim wall_field(const StepArgs& a, int side, int m, i
   return p;
 }
 
+// Writes the ghost entries to wu (4 ledger planes) and wn (NP population
+// planes); the step kernel reads the same buffer through a.wU / a.wN.
 template <typename T>
-__global__ void wall_ghost_kernel(StepArgs a) {
+__global__ void wall_ghost_kernel(StepArgs a, long long* wu, T* wn) {
   const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= a.wall_n) return;
   const int L = a.wall_len;
@@ -1917,8 +1921,6 @@ __global__ void wall_ghost_kernel(StepArgs a) {
   const double u2 = -a.tau1 * ce * p;
   const double g20 = u2 * (sxx - 2.0 * d * icv) - g00, g02 = u2 * (syy - 2.0 * d * icv) - g00;
   const double g11 = u2 * sxy;
-  T* wn = static_cast<T*>(const_cast<void*>(a.wN));
-  long long* wu = const_cast<long long*>(a.wU);
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const double cx = node<4, double>(i & 3), cy = node<4, double>(i >> 2);
@@ -2444,10 +2446,11 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
   return hipGetLastError();
 }
 
-hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, hipStream_t st) {
+hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, long long* wU, void* wN,
+                              hipStream_t st) {
   const dim3 grid(unsigned((a.wall_n + 255) / 256)), block(256);
-  if (fp64) hipLaunchKernelGGL(wall_ghost_kernel<double>, grid, block, 0, st, a);
-  else hipLaunchKernelGGL(wall_ghost_kernel<float>, grid, block, 0, st, a);
+  if (fp64) hipLaunchKernelGGL(wall_ghost_kernel<double>, grid, block, 0, st, a, wU, static_cast<double*>(wN));
+  else hipLaunchKernelGGL(wall_ghost_kernel<float>, grid, block, 0, st, a, wU, static_cast<float*>(wN));
   return hipGetLastError();
 }
 
