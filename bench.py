@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # gfx950: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32
-# is disabled in this build, so FP32 and FP64 vector ops share this peak.
+# is not used (the kernels are compiled without packed FP32 instructions), so FP32
+# and FP64 vector ops share this peak.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # Algorithmic bytes per 2D cell-update: the persistent state read once and
@@ -314,7 +315,7 @@ def d2q25_leg(n, steps, warmup):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2302_00310_amd import inputs, pond
