@@ -341,6 +341,10 @@ def main():
     out["roofline"] = {"bound": "alu", "achieved": achieved_tf, "peak": VALU_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved_tf / VALU_PEAK_TFLOPS,
                        "traffic": measured_traffic(a.n), "kernel": "step_batch_kernel<2,float,0,0>",
+                       # the FP32 rate with packed (two-wide) instructions, which the
+                       # kernels do not use, for comparison
+                       "peak_packed_fp32": 2 * VALU_PEAK_TFLOPS,
+                       "frac_of_packed_fp32": achieved_tf / (2 * VALU_PEAK_TFLOPS),
                        "kernel_ms": kern_m, "flops_per_cell": flops}
     hbm = BYTES_PER_CELL["mixed"] * cells / (kern_m * 1e-3) / 1e9
     out["hbm_roofline"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
