@@ -168,3 +168,17 @@ def test_forced_channel_checkpoint_resume_bitwise(pond, tmp_path):
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("transform", [0, 1])
+def test_force_with_a_corrector_pass(pond, transform):
+    wl = CASES["vortex_box_37x33"]()
+    s = pond.Solver(wl, precision=FP64, transform=transform, n_corr=1)
+    o = oracle.Oracle(wl, transform=transform, n_corr=1)
+    try:
+        s.step(10)
+        o.step(10)
+        e = moment_errors(s.moments(), o.moments(), u_floor=1.0)
+        assert max(e.values()) <= 1e-12, e
+    finally:
+        s.close()

@@ -150,3 +150,17 @@ def test_walls_full_size_sampled_cells(pond):
         got = np.array([[float(a[y, x]) for a in m] for (x, y) in pts])
         e = moment_errors(tuple(got.T), tuple(ref.T), l2=(precision == MIXED))
         assert max(e.values()) <= (1e-12 if precision == FP64 else 1e-5), (precision, e)
+
+
+@pytest.mark.parametrize("limiter,n_corr", [(1, 0), (0, 1)])
+def test_walls_with_minmod_and_a_corrector_pass(pond, limiter, n_corr):
+    wl = CASES["cavity_35x34"]()
+    s = pond.Solver(wl, precision=FP64, limiter=limiter, n_corr=n_corr)
+    o = oracle.Oracle(wl, limiter=limiter, n_corr=n_corr)
+    try:
+        s.step(12)
+        o.step(12)
+        e = moment_errors(s.moments(), o.moments())
+        assert max(e.values()) <= 1e-12, e
+    finally:
+        s.close()
