@@ -59,9 +59,10 @@ enum { POND_D1Q4 = 1, POND_D2Q16 = 2, POND_D2Q9 = 3, POND_D2Q9_D2Q16 = 4, POND_D
 /* POND_D2Q25: the fourth-order f-lattice (tensor of the 5-point
    Gauss-Hermite rule, Table I) with the fourth-order Grad projection
    (Sec. III B, full invariant moment system): needs POND_TF_GRAD and dim 2;
-   no walls or body force.  Runs as three plain kernels per step with the
-   face data in the arena (not fused like D2Q16), not in the serving loop,
-   and pond_export_state does not cover it. */
+   no walls or body force.  Runs as four plain kernel launches per step
+   (cell pass, x- and y-face passes, update) with the face data in the
+   arena (not fused like D2Q16), not in the serving loop, and
+   pond_export_state does not cover it (POND_ERR_UNSUPPORTED). */
 /* POND_D2Q9: the second-order f-lattice everywhere.  POND_D2Q9_D2Q16: the
    multiscale deployment (Sec. III C, Sec. IV C) -- each step, D2Q16 within
    two cells of a cell whose gradient indicator
@@ -93,7 +94,8 @@ enum { POND_LIM_VANLEER = 0, POND_LIM_MINMOD = 1 };
 
 typedef struct {
   int dim, nx, ny;           /* dim 1 or 2; ny = 1 when dim = 1; nx, ny >= 4 (2D), nx >= 4 (1D) */
-  int lattice;               /* POND_D1Q4 (dim 1); POND_D2Q16, POND_D2Q9 or POND_D2Q9_D2Q16 (dim 2) */
+  int lattice;               /* POND_D1Q4 (dim 1); POND_D2Q16, POND_D2Q9, POND_D2Q9_D2Q16 or
+                                POND_D2Q25 (dim 2) */
   int transform;             /* POND_TF_* */
   int precision;             /* POND_FP64 or POND_MIXED */
   double gamma;              /* adiabatic exponent, > 1; C_v = 1/(gamma - 1) */
@@ -162,7 +164,8 @@ int pond_totals_fixed(pond_state* s, int64_t out[8], int* scale_bits);
 
 /* Waits for the stream and writes the populations f~ (Qf planes of nx*ny
    doubles, i = i_x + q i_y, nodes ascending), g~ (Qg planes) and the frame
-   (u_x, u_y, T planes) they are written in.  Any pointer may be NULL. */
+   (u_x, u_y, T planes) they are written in.  Any pointer may be NULL.
+   POND_ERR_UNSUPPORTED for POND_D2Q25 solves. */
 int pond_export_state(pond_state* s, double* f, double* g, double* frame);
 
 /* Per cell (row-major [ny][nx], host arrays, either may be NULL): the
