@@ -353,7 +353,7 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
   a.transform = c.transform;
   bool ext = c.accel[0] != 0.0 || c.accel[1] != 0.0;
   for (int k = 0; k < 2 * c.dim; ++k) ext |= c.bc[k] == POND_BC_WALL;
-  a.ms = s->L.ms ? 1 : (ext ? 2 : 0);
+  a.ms = s->L.ms ? (c.lattice == POND_D2Q9 ? 3 : 1) : (ext ? 2 : 0);
   if (twod) {
     a.tiles_x = (c.nx + kTX2 - 1) / kTX2;
     a.tiles_y = (c.ny + kTY2 - 1) / kTY2;

@@ -58,7 +58,7 @@ struct StepArgs {
   // the lattice n_in is written in, and the one this step uses and writes
   const unsigned char* lat_in;
   const unsigned char* lat_out;
-  int ms;                  // kernel mode: 0 D2Q16, 1 per-cell f-lattices, 2 D2Q16 with walls or force
+  int ms;                  // kernel mode: 0 D2Q16, 1 multiscale, 2 D2Q16 with walls or force, 3 D2Q9
   // walls: ghost layer k (1, 2) of side s at coordinate t along the wall is
   // entry (2 s + k - 1) wall_len + t of wall_n-long planes, written before
   // each step by the wall-ghost kernel and read by the tile loader
@@ -86,7 +86,7 @@ struct BatchEntry {
 // Step kernels by kind: transform t (0 Lagrange, 1 Grad) and mode ms (0:
 // D2Q16 everywhere; 1: per-cell f-lattices, D2Q9 or multiscale, Grad only;
 // 2: D2Q16 with walls or a body force -- their loader and update carry the
-// extra work, which the plain kernels leave out).
+// extra work, which the plain kernels leave out; 3: D2Q9 everywhere).
 constexpr int kind_of(int transform, int ms) { return transform + 2 * ms; }
 // kind_mask: bit kind_of(t, ms) set launches that kernel (a batch may hold
 // solves of several kinds; each kernel skips the others' blocks).

@@ -1652,7 +1652,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, Smem<D, T>& sm, int
   }
 }
 
-// MS: 0 D2Q16; 1 per-cell f-lattices; 2 D2Q16 with walls or a body force.
+// MS: 0 D2Q16; 1 per-cell f-lattices (multiscale); 2 D2Q16 with walls or a
+// body force; 3 D2Q9 everywhere (the D2Q9 body alone, with its own register
+// allocation).
 template <int D, typename T, int LIM, int TF, int MS = 0>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T>& sm) {
   using G = Geo<D>;
@@ -1702,6 +1704,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
 #pragma unroll
         for (int i = 0; i < 9; ++i) sm.P[i * G::NH + h] = r * wg<D, T>(i) + apre * n[i];
       }
+    } else if constexpr (D == 2 && MS == 3) {
+      // D2Q9 everywhere: every slot on D2Q9, no switch
+      sm.Lat[h] = 3;
+      qe_half<D, T>(n, n + QF, kap, false);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) sm.P[i * G::NH + h] = r * wg<D, T>(i) + apre * n[i];
     } else {
       qe_half<D, T>(n, n + QF, kap);
 #pragma unroll
@@ -1726,6 +1734,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, Smem<D, T
     if (!any9) step_body<D, T, LIM, TF, 4>(a, sm, tid, x0, y0, kappa);
     else if (!any16) step_body<D, T, LIM, TF, 3>(a, sm, tid, x0, y0, kappa);
     else step_body<D, T, LIM, TF, 1>(a, sm, tid, x0, y0, kappa);
+  } else if constexpr (D == 2 && MS == 3) {
+    step_body<D, T, LIM, TF, 3>(a, sm, tid, x0, y0, kappa);
   } else {
     step_body<D, T, LIM, TF, 0, MS == 2>(a, sm, tid, x0, y0, kappa);
   }
@@ -2438,6 +2448,10 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
   if (kind_mask & (1u << kind_of(TF_GRAD, 2))) {
     if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 2>), grid, block, 0, st, tab, n, parity);
     else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 2>), grid, block, 0, st, tab, n, parity);
+  }
+  if (kind_mask & (1u << kind_of(TF_GRAD, 3))) {
+    if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 3>), grid, block, 0, st, tab, n, parity);
+    else hipLaunchKernelGGL((step_batch_kernel<2, float, TF_GRAD, 3>), grid, block, 0, st, tab, n, parity);
   }
   if (kind_mask & (1u << kind_of(TF_GRAD, 1))) {
     if (fp64) hipLaunchKernelGGL((step_batch_kernel<2, double, TF_GRAD, 1>), grid, block, 0, st, tab, n, parity);
