@@ -184,6 +184,10 @@ int upload_table(pond_state* s) {
     e.args[par].U_out = s->U[1 - par];
     e.args[par].lat_in = s->lat[par];
     e.args[par].lat_out = s->lat[1 - par];
+    if (s->cfg.lattice == POND_D2Q9_D2Q16) {
+      e.args[par].q16_in = s->q16 + par;
+      e.args[par].q16_out = s->q16 + 1 - par;
+    }
   }
   e.tile_begin = 0;
   e.tiles = s->args.tiles_x * s->args.tiles_y;
@@ -233,7 +237,9 @@ int pond_create(const pond_config* cfg, void* dev_arena, size_t arena_bytes, voi
   s->n[1] = p; p += L.pop_bytes;
   s->U[0] = reinterpret_cast<long long*>(p); p += L.led_bytes;
   s->U[1] = reinterpret_cast<long long*>(p); p += L.led_bytes;
-  s->flag = reinterpret_cast<int*>(p); p += 256;
+  s->flag = reinterpret_cast<int*>(p);
+  s->q16 = s->flag + 16;  // in the flag word's 256-byte slot
+  p += 256;
   s->inflow_dev = reinterpret_cast<long long*>(p); p += 256;
   s->tab = reinterpret_cast<BatchEntry*>(p); p += L.tab_bytes;
   s->red = reinterpret_cast<long long*>(p); p += L.red_bytes;
@@ -338,6 +344,12 @@ int pond_init_fields(pond_state* s, const double* rho, const double* ux, const d
     POND_HIP(hipMemsetAsync(s->lat[1], q1, s->L.lat_bytes, s->stream));
     POND_HIP(hipMemsetAsync(s->theta, 0, s->L.theta_bytes, s->stream));
   }
+  {
+    // "some cell may be on D2Q16" for both lattice planes until a switch says
+    // otherwise (1 is always safe: it only turns off the all-D2Q9 fast path)
+    const int one[2] = {1, 1};
+    POND_HIP(hipMemcpyAsync(s->q16, one, sizeof one, hipMemcpyHostToDevice, s->stream));
+  }
   POND_HIP(hipStreamSynchronize(s->stream));
   s->cur = 0;
   s->nstep = 0;
@@ -414,7 +426,8 @@ int pond_step(pond_state* s, int nsteps) {
       if (s->cfg.lattice == POND_D2Q9_D2Q16) {
         // this step's f-lattices, from the state at its start
         StepArgs a = s->args;
-        POND_HIP(launch_switch(a, s->U[s->cur], s->cfg.ms_threshold, s->cfg.gamma, s->theta,
+        POND_HIP(launch_switch(a, s->U[s->cur], s->cfg.ms_threshold, s->cfg.gamma,
+                               s->q16 + 1 - s->cur, s->theta,
                                s->lat[1 - s->cur], s->stream));
       }
       if (s->L.wall_bytes) {
@@ -423,8 +436,11 @@ int pond_step(pond_state* s, int nsteps) {
         a.U_in = s->U[s->cur];
         POND_HIP(launch_wall_ghosts(s->L.fp64, a, s->wU, s->wN, s->stream));
       }
-      POND_HIP(launch_step_batch(s->L.fp64, 1u << kind_of(s->cfg.transform, s->args.ms), s->tab, 1,
-                                 s->args.tiles_x * s->args.tiles_y, s->cur, s->stream));
+      unsigned mask = 1u << kind_of(s->cfg.transform, s->args.ms);
+      // a multiscale step may run in the D2Q9 kernel (all cells on D2Q9)
+      if (s->cfg.lattice == POND_D2Q9_D2Q16) mask |= 1u << kind_of(POND_TF_GRAD, 3);
+      POND_HIP(launch_step_batch(s->L.fp64, mask, s->tab, 1, s->args.tiles_x * s->args.tiles_y,
+                                 s->cur, s->stream));
     } else {
       StepArgs a = s->args;
       a.n_in = s->n[s->cur];
@@ -644,6 +660,13 @@ int pond_load(pond_state* s, const char* path) {
   }
   const int zero = 0;  // a checkpoint holds a healthy state: clear the status flag
   POND_HIP(hipMemcpy(s->flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+  // whether the restored lattice plane has a D2Q16 cell, as the switch
+  // records it each step (so a resumed run takes the same kernels)
+  int any16 = lat_n ? 0 : 1;
+  for (size_t k = 0; k < lat_n; ++k)
+    any16 |= buf[h.pop_bytes + h.led_bytes + k] == 4;
+  const int q16[2] = {any16, any16};
+  POND_HIP(hipMemcpy(s->q16, q16, sizeof q16, hipMemcpyHostToDevice));
   return upload_table(s);
 }
 

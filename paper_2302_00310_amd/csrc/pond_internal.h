@@ -59,6 +59,10 @@ struct StepArgs {
   const unsigned char* lat_in;
   const unsigned char* lat_out;
   int ms;                  // kernel mode: 0 D2Q16, 1 multiscale, 2 D2Q16 with walls or force, 3 D2Q9
+  // multiscale: words that are 0 when no cell of lat_in / lat_out is on
+  // D2Q16 (null elsewhere); such a step runs in the D2Q9 kernel
+  const int* q16_in;
+  const int* q16_out;
   // walls: ghost layer k (1, 2) of side s at coordinate t along the wall is
   // entry (2 s + k - 1) wall_len + t of wall_n-long planes, written before
   // each step by the wall-ghost kernel and read by the tile loader
@@ -94,7 +98,9 @@ hipError_t launch_step_batch(bool fp64, unsigned kind_mask, const BatchEntry* ta
                              int total_tiles, int parity, hipStream_t st);
 // Multiscale switch of one solve: the indicator theta per cell from the
 // ledger's frames, then the f-lattice (4 or 3 nodes per axis) per cell.
+// q16_out: set to 1 if any cell gets D2Q16 (cleared first).
 hipError_t launch_switch(const StepArgs& a, const long long* U, double threshold, double gamma,
+                         int* q16_out,
                          double* theta, unsigned char* lat_out, hipStream_t st);
 hipError_t launch_step_1d(bool fp64, const StepArgs& a, hipStream_t st);
 // One step of a D2Q25 solve (cell pass, x- and y-face passes, update),

@@ -1780,7 +1780,15 @@ __global__ void __launch_bounds__(kThreads, (D == 2 && sizeof(T) == 4) ? 2 : 1)
   const int tile = b - tab[lo].tile_begin;
   // one kernel per transform and f-lattice mode (each keeps its own
   // register allocation); blocks of solves of another kind leave at once
-  if (a.transform != TF || a.ms != MS) return;
+  if (a.transform != TF) return;
+  if constexpr (MS == 1 || MS == 3) {
+    // a multiscale step whose f-lattice maps before and after it are all
+    // D2Q9 (no cell stored on or moving to D2Q16) runs in the D2Q9 kernel
+    const bool all9 = a.ms == 1 && a.q16_in && *a.q16_in == 0 && *a.q16_out == 0;
+    if (MS == 1 ? (a.ms != 1 || all9) : (a.ms != 3 && !all9)) return;
+  } else {
+    if (a.ms != MS) return;
+  }
   // the limiter is uniform over a solve: one straight-line body per kind
   if (a.limiter == LIM_MINMOD) step_tile<D, T, LIM_MINMOD, TF, MS>(a, tile, sm);
   else step_tile<D, T, LIM_VANLEER, TF, MS>(a, tile, sm);
@@ -1813,8 +1821,11 @@ __device__ __forceinline__ Frame frame_at(const StepArgs& a, const long long* U,
   return gauge(u, a);
 }
 
-__global__ void switch_theta_kernel(StepArgs a, const long long* U, double gamma, double* theta) {
+__global__ void switch_theta_kernel(StepArgs a, const long long* U, double gamma, double* theta,
+                                    int* q16_out) {
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // clears the "some cell on D2Q16" word the lattice kernel sets next
+  if (k == 0) *q16_out = 0;
   if (k >= a.cells) return;
   const int x = int(k % size_t(a.nx)), y = int(k / size_t(a.nx));
   const Frame xp = frame_at(a, U, x + 1, y), xm = frame_at(a, U, x - 1, y);
@@ -1829,12 +1840,12 @@ __global__ void switch_theta_kernel(StepArgs a, const long long* U, double gamma
 }
 
 __global__ void switch_lattice_kernel(StepArgs a, const double* theta, double threshold,
-                                      unsigned char* lat) {
+                                      unsigned char* lat, int* q16_out) {
   const size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= a.cells) return;
-  const int x = int(k % size_t(a.nx)), y = int(k / size_t(a.nx));
+  const bool in = k < a.cells;
+  const int x = in ? int(k % size_t(a.nx)) : 0, y = in ? int(k / size_t(a.nx)) : 0;
   bool hi = false;
-  for (int j = -2; j <= 2; ++j) {
+  for (int j = in ? -2 : 3; j <= 2; ++j) {
     for (int i = -2; i <= 2; ++i) {
       // the ghost rule of the populations: x first; past an inflow side
       // the nearest interior cell, without wrapping y
@@ -1845,7 +1856,11 @@ __global__ void switch_lattice_kernel(StepArgs a, const double* theta, double th
       hi |= theta[size_t(sx) + size_t(a.nx) * size_t(sy)] >= threshold;
     }
   }
-  lat[k] = hi ? 4 : 3;
+  if (in) lat[k] = hi ? 4 : 3;
+  // "some cell on D2Q16": one vote per block, and no atomic once it is set
+  // (a word every wave raised would serialise thousands of atomics)
+  const int any = __syncthreads_or(hi);
+  if (threadIdx.x == 0 && any && *static_cast<volatile int*>(q16_out) == 0) atomicOr(q16_out, 1);
 }
 
 // --------------------------------------------------------------------------
@@ -2469,10 +2484,11 @@ hipError_t launch_wall_ghosts(bool fp64, const StepArgs& a, long long* wU, void*
 }
 
 hipError_t launch_switch(const StepArgs& a, const long long* U, double threshold, double gamma,
+                         int* q16_out,
                          double* theta, unsigned char* lat_out, hipStream_t st) {
   const dim3 grid(unsigned((a.cells + 255) / 256)), block(256);
-  hipLaunchKernelGGL(switch_theta_kernel, grid, block, 0, st, a, U, gamma, theta);
-  hipLaunchKernelGGL(switch_lattice_kernel, grid, block, 0, st, a, theta, threshold, lat_out);
+  hipLaunchKernelGGL(switch_theta_kernel, grid, block, 0, st, a, U, gamma, theta, q16_out);
+  hipLaunchKernelGGL(switch_lattice_kernel, grid, block, 0, st, a, theta, threshold, lat_out, q16_out);
   return hipGetLastError();
 }
 

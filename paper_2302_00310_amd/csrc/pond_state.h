@@ -44,6 +44,7 @@ struct pond_state {
   void* n[2] = {nullptr, nullptr};        // non-equilibrium population planes (ping-pong)
   long long* U[2] = {nullptr, nullptr};   // conserved-moment ledger planes (ping-pong)
   int* flag = nullptr;
+  int* q16 = nullptr;                     // multiscale: per lattice plane, 0 if no cell is on D2Q16
   long long* inflow_dev = nullptr;        // [4][4] fixed-point moments of the inflow states
   pond::BatchEntry* tab = nullptr;        // one-entry step table (2D): the kernel serving uses
   long long* red = nullptr;
