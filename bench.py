@@ -39,10 +39,10 @@ BYTES_PER_CELL = {"mixed": 2 * (25 * 4 + 4 * 8), "fp64": 2 * (25 * 8 + 4 * 8)}
 KERNEL_SOURCES = ("paper_2302_00310_amd/csrc/pond_kernels.hip",
                   "paper_2302_00310_amd/csrc/pond_internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "26a597915baef81b00bfa8e9e37874cb7d1b1e467040e77750ee9869b0f19042",
+    "sha256": "99dcd79c640ca4cf7b5615da5def6e4ebca0329a8b198f629b94455f783bdf35",
     "n": 2048,
-    "fetch_bytes": 1.66254e+09,
-    "write_bytes": 7.84237e+08,
+    "fetch_bytes": 1.64760e+09,
+    "write_bytes": 7.89201e+08,
 }
 
 
