@@ -85,6 +85,27 @@ def flops_per_cell_2d(n_corr: int = 0) -> int:
     return 2 * face + cell
 
 
+def flops_per_cell_d2q25() -> int:
+    """Floating-point operations of one D2Q25 cell-update as its kernels
+    specify them (FMA = 2, n_corr = 0).  Grad's map of order 4 on D2Q25:
+    Hermite values at the 2 x 5 shifted nodes (2 x 5 x 5), the moment stage
+    (125 + 75 FMA) and the expansion (75 + 100 FMA); of order 2 on D2Q9:
+    (2 x 3 x 3) + (27 + 18 + 18 + 18 FMA).  Per face (two per cell): 8
+    stencil projections, reconstruction (34 x 30), FP64 face moments
+    (25 x 10 + 9), face equilibrium (34 products and one projection),
+    inversion and fluxes (34 x 2 + 25 x 10 + 9 x 2).  Per cell: the cell pass
+    (QE half step 25 x 10 + 9 x 4, phi-bar-plus 34 x 2, frame 30), four
+    face-to-cell projections with their flux products (34 x 3), the update
+    (34 x 4), the re-gauge projection and the second QE half step."""
+    f_map = 2 * 5 * 5 + 2 * (125 + 75 + 75 + 100)
+    g_map = 2 * 3 * 3 + 2 * (27 + 18 + 18 + 18)
+    proj = f_map + g_map
+    face = 8 * proj + 34 * 30 + (25 * 10 + 9) + (34 + proj) + (34 * 2 + 25 * 10 + 9 * 2)
+    qe = 25 * 10 + 9 * 4
+    cell = (qe + 34 * 2 + 30) + 4 * (proj + 34 * 3) + 34 * 4 + proj + qe + 30
+    return 2 * face + cell
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -309,6 +330,12 @@ def d2q25_leg(n, steps, warmup):
         wall, kern = time_path(wl, prec, steps, warmup, transform=pond.POND_TF_GRAD, lattice=lat)
         out[name] = {"value": cells * steps / wall, "unit": "cell-updates/s", "ms_per_step": kern}
     out["d2q25_over_d2q16_mixed"] = out["d2q25_mixed"]["value"] / out["d2q16_mixed"]["value"]
+    flops = flops_per_cell_d2q25()
+    for name in ("d2q25_mixed", "d2q25_fp64"):
+        tf = flops * cells / (out[name]["ms_per_step"] * 1e-3) / 1e12
+        out[name]["alu_roofline"] = {"bound": "alu", "achieved": tf, "peak": VALU_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": tf / VALU_PEAK_TFLOPS,
+                                     "flops_per_cell": flops}
     return out
 
 
