@@ -161,6 +161,8 @@ int upload_table(pond_server* S) {
       e.args[par].n_out = s->n[1 - in];
       e.args[par].U_in = s->U[in];
       e.args[par].U_out = s->U[1 - in];
+      e.args[par].lat_in = s->lat[in];
+      e.args[par].lat_out = s->lat[1 - in];
     }
     e.tile_begin = tile;
     e.tiles = tiles_of(s->cfg);
@@ -169,7 +171,7 @@ int upload_table(pond_server* S) {
   S->n_tab = int(S->active.size());
   S->total_tiles = tile;
   S->tf_mask = 0;
-  for (Job* j : S->active) S->tf_mask |= 1u << kind_of(j->cfg.transform, 0);
+  for (Job* j : S->active) S->tf_mask |= 1u << kind_of(j->cfg.transform, j->st->args.ms);
   S->phase = 0;
   hipError_t err = hipMemcpyAsync(S->dev_tab, S->host_tab, sizeof(BatchEntry) * S->n_tab,
                                   hipMemcpyHostToDevice, S->stream);
@@ -404,13 +406,11 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   int rc = validate(&c);
   if (rc) return rc;
   if (c.dim != 2) return fail(POND_ERR_UNSUPPORTED, "serving runs 2D solves");
-  if (c.lattice != POND_D2Q16)
-    return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 f-lattice");
+  if (c.lattice != POND_D2Q16 && c.lattice != POND_D2Q9)
+    return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 and D2Q9 f-lattices");
   if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
   for (int k = 0; k < 4; ++k)
     if (c.bc[k] == POND_BC_WALL) return fail(POND_ERR_UNSUPPORTED, "serving runs solves without walls");
-  if (c.accel[0] != 0.0 || c.accel[1] != 0.0)
-    return fail(POND_ERR_UNSUPPORTED, "serving runs solves without a body force");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");
   const size_t need = layout_of(&c).total;

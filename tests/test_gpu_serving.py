@@ -39,7 +39,7 @@ def _alone(pond, wl, steps, transform=0):
     return [a.reshape(-1) for a in m]
 
 
-def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0, transforms=None):
+def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0, transforms=None, lattices=None):
     import torch
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     srv = pond.pond_server_create(arena.data_ptr(), arena_bytes, 0, max_active)
@@ -47,7 +47,8 @@ def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0, transforms=Non
     try:
         for k, (wl, steps) in enumerate(jobs):
             cfg = pond.make_config(wl, precision=pond.POND_MIXED,
-                                   transform=transforms[k] if transforms else 0)
+                                   transform=transforms[k] if transforms else 0,
+                                   lattice=lattices[k] if lattices else None)
             ids.append(pond.pond_submit(srv, cfg, *wl.fields(), steps, tag=k))
         out = {}
         t_end = time.time() + timeout
@@ -169,3 +170,40 @@ def test_input_outside_the_methods_range_is_reported(pond):
         s.close()
     got = _serve(pond, [(wl, 20)], 1 << 28)
     assert got[0][0] == -4
+
+
+def test_d2q9_and_forced_solves_share_a_batch(pond):
+    """D2Q16 (Lagrange and Grad), D2Q9 and body-force solves in one stream:
+    each result equals the same solve run alone, bit for bit (the batch
+    launches one step kernel per kind; each skips the others' blocks)."""
+    vort = inputs.vortex_2d(40, steps=1, mach=1.0, noise=1e-3, seed=31, ny=36)
+    quad = inputs.quadrants_2d(48, steps=1, seed=32, ny=40)
+    forced = inputs.vortex_2d(44, steps=1, mach=0.8, noise=1e-3, seed=33, ny=38)
+    forced.accel = [0.4, -0.2]
+    jobs = [(vort, 30), (quad, 25), (forced, 28), (quad, 22), (vort, 26)]
+    transforms = [0, 1, 0, 1, 1]
+    lattices = [pond.POND_D2Q16, pond.POND_D2Q9, pond.POND_D2Q16, pond.POND_D2Q16, pond.POND_D2Q9]
+    got = _serve(pond, jobs, 1 << 28, transforms=transforms, lattices=lattices)
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, _ = got[k]
+        assert rc == pond.POND_OK, k
+        s = pond.Solver(wl, precision=pond.POND_MIXED, transform=transforms[k], lattice=lattices[k])
+        s.step(steps)
+        alone = [a.reshape(-1) for a in s.moments()]
+        s.close()
+        for a, b in zip(m, alone):
+            assert np.array_equal(a, b), k
+
+
+def test_walls_are_rejected_at_submit(pond):
+    import torch
+    wl = inputs.thermal_couette_2d(32, steps=1)
+    cfg = pond.make_config(wl, precision=pond.POND_MIXED)
+    need = pond.pond_state_bytes(cfg)
+    arena = torch.empty(2 * need, dtype=torch.uint8, device="cuda")
+    srv = pond.pond_server_create(arena.data_ptr(), 2 * need, 0, 4)
+    try:
+        with pytest.raises(pond.PondError):
+            pond.pond_submit(srv, cfg, *wl.fields(), 10)
+    finally:
+        pond.pond_server_destroy(srv)
