@@ -188,11 +188,25 @@ int run_steps(pond_server* S, int K) {
     const double t = S->now();
     hipError_t err = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
-    for (int j = 0; j < K; ++j)
-      launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab, S->total_tiles, (par0 + j) & 1,
-                        S->stream);
+    hipError_t lerr = hipSuccess;
+    for (int j = 0; j < K; ++j) {
+      const int par = (par0 + j) & 1;
+      // walled solves: ghost layers from the ledger at the start of the step
+      for (size_t k = 0; k < S->active.size() && lerr == hipSuccess; ++k) {
+        pond_state* s = S->active[k]->st;
+        if (s->L.wall_bytes)
+          lerr = launch_wall_ghosts(false, S->host_tab[k].args[par], s->wU, s->wN, S->stream);
+      }
+      if (lerr == hipSuccess)
+        lerr = launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab, S->total_tiles, par,
+                                 S->stream);
+    }
     hipGraph_t g = nullptr;
     err = hipStreamEndCapture(S->stream, &g);
+    if (err == hipSuccess && lerr != hipSuccess) {
+      hipGraphDestroy(g);
+      return hip_fail(lerr, "batched step launch");
+    }
     if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
     hipGraphExec_t ex = nullptr;
     err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -409,8 +423,6 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   if (c.lattice != POND_D2Q16 && c.lattice != POND_D2Q9)
     return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 and D2Q9 f-lattices");
   if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
-  for (int k = 0; k < 4; ++k)
-    if (c.bc[k] == POND_BC_WALL) return fail(POND_ERR_UNSUPPORTED, "serving runs solves without walls");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");
   const size_t need = layout_of(&c).total;

@@ -195,15 +195,18 @@ def test_d2q9_and_forced_solves_share_a_batch(pond):
             assert np.array_equal(a, b), k
 
 
-def test_walls_are_rejected_at_submit(pond):
-    import torch
-    wl = inputs.thermal_couette_2d(32, steps=1)
-    cfg = pond.make_config(wl, precision=pond.POND_MIXED)
-    need = pond.pond_state_bytes(cfg)
-    arena = torch.empty(2 * need, dtype=torch.uint8, device="cuda")
-    srv = pond.pond_server_create(arena.data_ptr(), 2 * need, 0, 4)
-    try:
-        with pytest.raises(pond.PondError):
-            pond.pond_submit(srv, cfg, *wl.fields(), 10)
-    finally:
-        pond.pond_server_destroy(srv)
+def test_walled_solves_share_a_batch(pond):
+    """Walled solves (each launches its ghost-layer kernel before every batched
+    step), one of them forced, served beside periodic ones: each result equals
+    the same solve alone, bit for bit."""
+    couette = inputs.thermal_couette_2d(36, nx=20, steps=1)
+    channel = inputs.poiseuille_2d(28, nx=24, steps=1)
+    vort = inputs.vortex_2d(40, steps=1, mach=1.0, noise=1e-3, seed=34, ny=36)
+    jobs = [(couette, 40), (vort, 30), (channel, 35), (couette, 17)]
+    transforms = [0, 1, 1, 1]
+    got = _serve(pond, jobs, 1 << 28, transforms=transforms)
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, _ = got[k]
+        assert rc == pond.POND_OK, k
+        for a, b in zip(m, _alone(pond, wl, steps, transforms[k])):
+            assert np.array_equal(a, b), k
