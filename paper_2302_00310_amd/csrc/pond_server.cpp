@@ -163,6 +163,10 @@ int upload_table(pond_server* S) {
       e.args[par].U_out = s->U[1 - in];
       e.args[par].lat_in = s->lat[in];
       e.args[par].lat_out = s->lat[1 - in];
+      if (s->cfg.lattice == POND_D2Q9_D2Q16) {
+        e.args[par].q16_in = s->q16 + in;
+        e.args[par].q16_out = s->q16 + 1 - in;
+      }
     }
     e.tile_begin = tile;
     e.tiles = tiles_of(s->cfg);
@@ -171,7 +175,11 @@ int upload_table(pond_server* S) {
   S->n_tab = int(S->active.size());
   S->total_tiles = tile;
   S->tf_mask = 0;
-  for (Job* j : S->active) S->tf_mask |= 1u << kind_of(j->cfg.transform, j->st->args.ms);
+  for (Job* j : S->active) {
+    S->tf_mask |= 1u << kind_of(j->cfg.transform, j->st->args.ms);
+    // a multiscale step may run in the D2Q9 kernel (all cells on D2Q9)
+    if (j->cfg.lattice == POND_D2Q9_D2Q16) S->tf_mask |= 1u << kind_of(POND_TF_GRAD, 3);
+  }
   S->phase = 0;
   hipError_t err = hipMemcpyAsync(S->dev_tab, S->host_tab, sizeof(BatchEntry) * S->n_tab,
                                   hipMemcpyHostToDevice, S->stream);
@@ -191,11 +199,18 @@ int run_steps(pond_server* S, int K) {
     hipError_t lerr = hipSuccess;
     for (int j = 0; j < K; ++j) {
       const int par = (par0 + j) & 1;
-      // walled solves: ghost layers from the ledger at the start of the step
+      // from the ledger at the start of the step: the f-lattice map of each
+      // multiscale solve, the ghost layers of each walled one
       for (size_t k = 0; k < S->active.size() && lerr == hipSuccess; ++k) {
         pond_state* s = S->active[k]->st;
-        if (s->L.wall_bytes)
-          lerr = launch_wall_ghosts(false, S->host_tab[k].args[par], s->wU, s->wN, S->stream);
+        const StepArgs& a = S->host_tab[k].args[par];
+        if (s->cfg.lattice == POND_D2Q9_D2Q16) {
+          const int out = a.lat_out == s->lat[1] ? 1 : 0;  // the plane this step writes
+          lerr = launch_switch(a, a.U_in, s->cfg.ms_threshold, s->cfg.gamma, s->q16 + out,
+                               s->theta, s->lat[out], S->stream);
+        }
+        if (lerr == hipSuccess && s->L.wall_bytes)
+          lerr = launch_wall_ghosts(false, a, s->wU, s->wN, S->stream);
       }
       if (lerr == hipSuccess)
         lerr = launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab, S->total_tiles, par,
@@ -420,8 +435,7 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   int rc = validate(&c);
   if (rc) return rc;
   if (c.dim != 2) return fail(POND_ERR_UNSUPPORTED, "serving runs 2D solves");
-  if (c.lattice != POND_D2Q16 && c.lattice != POND_D2Q9)
-    return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 and D2Q9 f-lattices");
+  if (c.lattice == POND_D2Q25) return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 and D2Q9 f-lattices");
   if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");

@@ -210,3 +210,33 @@ def test_walled_solves_share_a_batch(pond):
         assert rc == pond.POND_OK, k
         for a, b in zip(m, _alone(pond, wl, steps, transforms[k])):
             assert np.array_equal(a, b), k
+
+
+def test_multiscale_solves_share_a_batch(pond):
+    """Multiscale solves (each launches its D2Q9/D2Q16 switch before every
+    batched step; a uniform one runs all-D2Q9 steps in the D2Q9 kernel) served
+    beside D2Q16 and D2Q9 ones: each result equals the same solve alone, bit
+    for bit, and the switch is seen to pick both lattices."""
+    quad = inputs.quadrants_2d(48, steps=1, seed=35, ny=40)
+    # uniform flow: the switch indicator is zero everywhere (all-D2Q9 steps)
+    smooth = inputs.vortex_2d(40, steps=1, mach=0.3, noise=0.0, seed=36, ny=36)
+    smooth.rho[:], smooth.ux[:], smooth.uy[:], smooth.p[:] = 1.0, 0.3, -0.1, 1.0
+    vort = inputs.vortex_2d(44, steps=1, mach=1.5, noise=1e-3, seed=37, ny=38)
+    jobs = [(quad, 30), (smooth, 25), (vort, 28), (quad, 21), (vort, 19)]
+    ms = pond.POND_D2Q9_D2Q16
+    lattices = [ms, ms, pond.POND_D2Q16, pond.POND_D2Q9, ms]
+    transforms = [1] * len(jobs)
+    got = _serve(pond, jobs, 1 << 28, transforms=transforms, lattices=lattices)
+    q16_cells = {}
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, _ = got[k]
+        assert rc == pond.POND_OK, k
+        s = pond.Solver(wl, precision=pond.POND_MIXED, transform=1, lattice=lattices[k])
+        s.step(steps)
+        alone = [a.reshape(-1) for a in s.moments()]
+        if lattices[k] == ms:
+            q16_cells[k] = int((s.lattice_map()[0] == 16).sum())
+        s.close()
+        for a, b in zip(m, alone):
+            assert np.array_equal(a, b), k
+    assert q16_cells[1] == 0 and q16_cells[0] > 0
