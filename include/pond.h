@@ -215,10 +215,9 @@ typedef struct {
 int pond_server_create(void* dev_arena, size_t bytes, void* hip_stream, int max_active,
                        pond_server** out);
 /* Copies the request's inputs and queues it; never waits for the GPU.
-   POND_ERR_REJECTED if its footprint exceeds the whole arena.  Serves 2D
-   mixed-precision solves on the D2Q16, D2Q9 or multiscale D2Q9_D2Q16
-   f-lattice, with walls or a body force where pond_create accepts them;
-   POND_ERR_UNSUPPORTED for D2Q25, FP64 and 1D. */
+   POND_ERR_REJECTED if its footprint exceeds the whole arena.  Serves every
+   2D mixed-precision solve that pond_create accepts (any f-lattice and
+   transform, walls, body force); POND_ERR_UNSUPPORTED for FP64 and 1D. */
 int pond_submit(pond_server* srv, const pond_request* req, uint64_t* id);
 /* POND_PENDING while the solve is queued or running; otherwise copies the
    moments into res' arrays, fills the times and returns the solve's status

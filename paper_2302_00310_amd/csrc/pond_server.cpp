@@ -169,13 +169,15 @@ int upload_table(pond_server* S) {
       }
     }
     e.tile_begin = tile;
-    e.tiles = tiles_of(s->cfg);
+    // D2Q25 solves run their own kernels, outside the batched step
+    e.tiles = s->L.q25 ? 0 : tiles_of(s->cfg);
     tile += e.tiles;
   }
   S->n_tab = int(S->active.size());
   S->total_tiles = tile;
   S->tf_mask = 0;
   for (Job* j : S->active) {
+    if (j->st->L.q25) continue;
     S->tf_mask |= 1u << kind_of(j->cfg.transform, j->st->args.ms);
     // a multiscale step may run in the D2Q9 kernel (all cells on D2Q9)
     if (j->cfg.lattice == POND_D2Q9_D2Q16) S->tf_mask |= 1u << kind_of(POND_TF_GRAD, 3);
@@ -211,8 +213,11 @@ int run_steps(pond_server* S, int K) {
         }
         if (lerr == hipSuccess && s->L.wall_bytes)
           lerr = launch_wall_ghosts(false, a, s->wU, s->wN, S->stream);
+        if (lerr == hipSuccess && s->L.q25)
+          lerr = launch_q25_step(false, a, s->qP, s->qfr, s->qfp[0], s->qfp[1], s->qff[0],
+                                 s->qff[1], s->qps[0], s->qps[1], S->stream);
       }
-      if (lerr == hipSuccess)
+      if (lerr == hipSuccess && S->total_tiles > 0)
         lerr = launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab, S->total_tiles, par,
                                  S->stream);
     }
@@ -435,7 +440,6 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   int rc = validate(&c);
   if (rc) return rc;
   if (c.dim != 2) return fail(POND_ERR_UNSUPPORTED, "serving runs 2D solves");
-  if (c.lattice == POND_D2Q25) return fail(POND_ERR_UNSUPPORTED, "serving runs the D2Q16 and D2Q9 f-lattices");
   if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");

@@ -240,3 +240,32 @@ def test_multiscale_solves_share_a_batch(pond):
         for a, b in zip(m, alone):
             assert np.array_equal(a, b), k
     assert q16_cells[1] == 0 and q16_cells[0] > 0
+
+
+def test_d2q25_solves_are_served(pond):
+    """D2Q25 solves run their own kernels inside the served chunk graphs, with
+    no tiles in the batched step: mixed with D2Q16 solves, and alone in the
+    server (no batched step at all).  Each result equals the same solve
+    alone, bit for bit.  The quadrants input of seed 38 (40 x 36) lies
+    outside the D2Q25 method's range: the FP64 oracle turns it non-finite on
+    its first step, and served it fails alone with POND_ERR_UNSTABLE."""
+    quad = inputs.quadrants_2d(40, steps=1, seed=3, ny=36)
+    bad = inputs.quadrants_2d(40, steps=1, seed=38, ny=36)
+    vort = inputs.vortex_2d(36, steps=1, mach=1.0, noise=1e-3, seed=39, ny=44)
+    q25, q16 = pond.POND_D2Q25, pond.POND_D2Q16
+    for jobs, lattices in (([(quad, 24), (vort, 30), (bad, 10), (vort, 17)], [q25, q16, q25, q25]),
+                           ([(vort, 20), (quad, 13)], [q25, q25])):
+        transforms = [1] * len(jobs)
+        got = _serve(pond, jobs, 1 << 28, transforms=transforms, lattices=lattices)
+        for k, (wl, steps) in enumerate(jobs):
+            rc, m, _ = got[k]
+            if wl is bad:
+                assert rc == -4  # POND_ERR_UNSTABLE
+                continue
+            assert rc == pond.POND_OK, k
+            s = pond.Solver(wl, precision=pond.POND_MIXED, transform=1, lattice=lattices[k])
+            s.step(steps)
+            alone = [a.reshape(-1) for a in s.moments()]
+            s.close()
+            for a, b in zip(m, alone):
+                assert np.array_equal(a, b), k
