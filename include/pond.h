@@ -61,8 +61,8 @@ enum { POND_D1Q4 = 1, POND_D2Q16 = 2, POND_D2Q9 = 3, POND_D2Q9_D2Q16 = 4, POND_D
    (Sec. III B, full invariant moment system): needs POND_TF_GRAD and dim 2;
    no walls or body force.  Runs as four plain kernel launches per step
    (cell pass, x- and y-face passes, update) with the face data in the
-   arena (not fused like D2Q16), not in the serving loop, and
-   pond_export_state does not cover it (POND_ERR_UNSUPPORTED). */
+   arena (not fused like D2Q16); pond_export_state does not cover it
+   (POND_ERR_UNSUPPORTED). */
 /* POND_D2Q9: the second-order f-lattice everywhere.  POND_D2Q9_D2Q16: the
    multiscale deployment (Sec. III C, Sec. IV C) -- each step, D2Q16 within
    two cells of a cell whose gradient indicator
@@ -192,12 +192,12 @@ int pond_destroy(pond_state* s);
 int pond_lattice_constants(double out[14]);
 
 /* ------------------------------------------------------------------------ */
-/* Serving: continuous batching of independent 2D solves.                   */
+/* Serving: continuous batching of independent solves.                      */
 /* ------------------------------------------------------------------------ */
 typedef struct pond_server pond_server;
 
 typedef struct {
-  pond_config cfg;                   /* dim must be 2 */
+  pond_config cfg;                   /* any configuration pond_create accepts */
   const double *rho, *ux, *uy, *p;   /* initial fields, copied by pond_submit */
   int nsteps;
   uint64_t tag;                      /* caller's label, echoed in the result */
@@ -215,9 +215,12 @@ typedef struct {
 int pond_server_create(void* dev_arena, size_t bytes, void* hip_stream, int max_active,
                        pond_server** out);
 /* Copies the request's inputs and queues it; never waits for the GPU.
-   POND_ERR_REJECTED if its footprint exceeds the whole arena.  Serves every
-   2D mixed-precision solve that pond_create accepts (any f-lattice and
-   transform, walls, body force); POND_ERR_UNSUPPORTED for FP64 and 1D. */
+   POND_ERR_REJECTED if its footprint exceeds the whole arena; the error of
+   validation for a configuration pond_create would reject.  Mixed-precision
+   2D solves on the D2Q16, D2Q9 and multiscale f-lattices share one batched
+   step kernel per step; FP64, 1D and D2Q25 solves run their own step
+   kernels in the same per-chunk graph.  A result equals the same solve run
+   alone through pond_step, bit for bit. */
 int pond_submit(pond_server* srv, const pond_request* req, uint64_t* id);
 /* POND_PENDING while the solve is queued or running; otherwise copies the
    moments into res' arrays, fills the times and returns the solve's status

@@ -196,6 +196,34 @@ int upload_table(pond_state* s) {
   return POND_OK;
 }
 
+int step_launches(pond_state* s, int in, hipStream_t st) {
+  StepArgs a = s->args;
+  a.n_in = s->n[in];
+  a.n_out = s->n[1 - in];
+  a.U_in = s->U[in];
+  a.U_out = s->U[1 - in];
+  if (s->L.q25) {
+    POND_HIP(launch_q25_step(s->L.fp64, a, s->qP, s->qfr, s->qfp[0], s->qfp[1], s->qff[0],
+                             s->qff[1], s->qps[0], s->qps[1], st));
+  } else if (s->cfg.dim == 2) {
+    if (s->cfg.lattice == POND_D2Q9_D2Q16) {
+      // this step's f-lattices, from the state at its start
+      POND_HIP(launch_switch(s->args, s->U[in], s->cfg.ms_threshold, s->cfg.gamma,
+                             s->q16 + 1 - in, s->theta, s->lat[1 - in], st));
+    }
+    // wall ghosts from the state at the start of this step
+    if (s->L.wall_bytes) POND_HIP(launch_wall_ghosts(s->L.fp64, a, s->wU, s->wN, st));
+    unsigned mask = 1u << kind_of(s->cfg.transform, s->args.ms);
+    // a multiscale step may run in the D2Q9 kernel (all cells on D2Q9)
+    if (s->cfg.lattice == POND_D2Q9_D2Q16) mask |= 1u << kind_of(POND_TF_GRAD, 3);
+    POND_HIP(launch_step_batch(s->L.fp64, mask, s->tab, 1, s->args.tiles_x * s->args.tiles_y,
+                               in, st));
+  } else {
+    POND_HIP(launch_step_1d(s->L.fp64, a, st));
+  }
+  return POND_OK;
+}
+
 }  // namespace pond
 
 using namespace pond;
@@ -414,41 +442,8 @@ int pond_step(pond_state* s, int nsteps) {
   if (!s || nsteps < 0) return fail(POND_ERR_INVALID, "bad arguments");
   if (!s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
   for (int k = 0; k < nsteps; ++k) {
-    if (s->L.q25) {
-      StepArgs a = s->args;
-      a.n_in = s->n[s->cur];
-      a.n_out = s->n[1 - s->cur];
-      a.U_in = s->U[s->cur];
-      a.U_out = s->U[1 - s->cur];
-      POND_HIP(launch_q25_step(s->L.fp64, a, s->qP, s->qfr, s->qfp[0], s->qfp[1], s->qff[0],
-                               s->qff[1], s->qps[0], s->qps[1], s->stream));
-    } else if (s->cfg.dim == 2) {
-      if (s->cfg.lattice == POND_D2Q9_D2Q16) {
-        // this step's f-lattices, from the state at its start
-        StepArgs a = s->args;
-        POND_HIP(launch_switch(a, s->U[s->cur], s->cfg.ms_threshold, s->cfg.gamma,
-                               s->q16 + 1 - s->cur, s->theta,
-                               s->lat[1 - s->cur], s->stream));
-      }
-      if (s->L.wall_bytes) {
-        // wall ghosts from the state at the start of this step
-        StepArgs a = s->args;
-        a.U_in = s->U[s->cur];
-        POND_HIP(launch_wall_ghosts(s->L.fp64, a, s->wU, s->wN, s->stream));
-      }
-      unsigned mask = 1u << kind_of(s->cfg.transform, s->args.ms);
-      // a multiscale step may run in the D2Q9 kernel (all cells on D2Q9)
-      if (s->cfg.lattice == POND_D2Q9_D2Q16) mask |= 1u << kind_of(POND_TF_GRAD, 3);
-      POND_HIP(launch_step_batch(s->L.fp64, mask, s->tab, 1, s->args.tiles_x * s->args.tiles_y,
-                                 s->cur, s->stream));
-    } else {
-      StepArgs a = s->args;
-      a.n_in = s->n[s->cur];
-      a.n_out = s->n[1 - s->cur];
-      a.U_in = s->U[s->cur];
-      a.U_out = s->U[1 - s->cur];
-      POND_HIP(launch_step_1d(s->L.fp64, a, s->stream));
-    }
+    const int rc = step_launches(s, s->cur, s->stream);
+    if (rc != POND_OK) return rc;
     s->cur ^= 1;
     s->nstep++;
   }

@@ -133,6 +133,11 @@ void drop_graphs(pond_server* S) {
   S->graphs.clear();
 }
 
+// Mixed-precision 2D solves on the D2Q16 / D2Q9 / multiscale f-lattices
+// share the batched step; the others (FP64, 1D, D2Q25) run their own step
+// launches in the same graph.
+bool batched(const pond_state* s) { return s->cfg.dim == 2 && !s->L.fp64 && !s->L.q25; }
+
 int tiles_of(const pond_config& c) {
   return ((c.nx + kTX2 - 1) / kTX2) * ((c.ny + kTY2 - 1) / kTY2);
 }
@@ -169,15 +174,14 @@ int upload_table(pond_server* S) {
       }
     }
     e.tile_begin = tile;
-    // D2Q25 solves run their own kernels, outside the batched step
-    e.tiles = s->L.q25 ? 0 : tiles_of(s->cfg);
+    e.tiles = batched(s) ? tiles_of(s->cfg) : 0;
     tile += e.tiles;
   }
   S->n_tab = int(S->active.size());
   S->total_tiles = tile;
   S->tf_mask = 0;
   for (Job* j : S->active) {
-    if (j->st->L.q25) continue;
+    if (!batched(j->st)) continue;
     S->tf_mask |= 1u << kind_of(j->cfg.transform, j->st->args.ms);
     // a multiscale step may run in the D2Q9 kernel (all cells on D2Q9)
     if (j->cfg.lattice == POND_D2Q9_D2Q16) S->tf_mask |= 1u << kind_of(POND_TF_GRAD, 3);
@@ -198,34 +202,38 @@ int run_steps(pond_server* S, int K) {
     const double t = S->now();
     hipError_t err = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
-    hipError_t lerr = hipSuccess;
-    for (int j = 0; j < K; ++j) {
+    int rc = POND_OK;
+    for (int j = 0; j < K && rc == POND_OK; ++j) {
       const int par = (par0 + j) & 1;
-      // from the ledger at the start of the step: the f-lattice map of each
-      // multiscale solve, the ghost layers of each walled one
-      for (size_t k = 0; k < S->active.size() && lerr == hipSuccess; ++k) {
+      for (size_t k = 0; k < S->active.size() && rc == POND_OK; ++k) {
         pond_state* s = S->active[k]->st;
         const StepArgs& a = S->host_tab[k].args[par];
-        if (s->cfg.lattice == POND_D2Q9_D2Q16) {
-          const int out = a.lat_out == s->lat[1] ? 1 : 0;  // the plane this step writes
-          lerr = launch_switch(a, a.U_in, s->cfg.ms_threshold, s->cfg.gamma, s->q16 + out,
-                               s->theta, s->lat[out], S->stream);
+        const int in = a.n_in == s->n[1] ? 1 : 0;  // the buffer this step reads
+        if (!batched(s)) {
+          rc = step_launches(s, in, S->stream);
+          continue;
         }
-        if (lerr == hipSuccess && s->L.wall_bytes)
-          lerr = launch_wall_ghosts(false, a, s->wU, s->wN, S->stream);
-        if (lerr == hipSuccess && s->L.q25)
-          lerr = launch_q25_step(false, a, s->qP, s->qfr, s->qfp[0], s->qfp[1], s->qff[0],
-                                 s->qff[1], s->qps[0], s->qps[1], S->stream);
+        // from the ledger at the start of the step: the f-lattice map of each
+        // multiscale solve, the ghost layers of each walled one
+        hipError_t e = hipSuccess;
+        if (s->cfg.lattice == POND_D2Q9_D2Q16)
+          e = launch_switch(a, a.U_in, s->cfg.ms_threshold, s->cfg.gamma, s->q16 + 1 - in,
+                            s->theta, s->lat[1 - in], S->stream);
+        if (e == hipSuccess && s->L.wall_bytes)
+          e = launch_wall_ghosts(false, a, s->wU, s->wN, S->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "switch / wall-ghost launch");
       }
-      if (lerr == hipSuccess && S->total_tiles > 0)
-        lerr = launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab, S->total_tiles, par,
-                                 S->stream);
+      if (rc == POND_OK && S->total_tiles > 0) {
+        const hipError_t e = launch_step_batch(false, S->tf_mask, S->dev_tab, S->n_tab,
+                                               S->total_tiles, par, S->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "batched step launch");
+      }
     }
     hipGraph_t g = nullptr;
     err = hipStreamEndCapture(S->stream, &g);
-    if (err == hipSuccess && lerr != hipSuccess) {
+    if (err == hipSuccess && rc != POND_OK) {
       hipGraphDestroy(g);
-      return hip_fail(lerr, "batched step launch");
+      return rc;
     }
     if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
     hipGraphExec_t ex = nullptr;
@@ -439,8 +447,6 @@ int pond_submit(pond_server* S, const pond_request* req, uint64_t* id) {
   const pond_config& c = req->cfg;
   int rc = validate(&c);
   if (rc) return rc;
-  if (c.dim != 2) return fail(POND_ERR_UNSUPPORTED, "serving runs 2D solves");
-  if (c.precision != POND_MIXED) return fail(POND_ERR_UNSUPPORTED, "serving runs the mixed-precision step");
   if (req->nsteps < 0) return fail(POND_ERR_INVALID, "nsteps must be >= 0");
   if (!req->rho || !req->ux || !req->uy || !req->p) return fail(POND_ERR_INVALID, "null field");
   const size_t need = layout_of(&c).total;

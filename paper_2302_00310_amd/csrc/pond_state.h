@@ -34,6 +34,9 @@ int hip_fail(hipError_t e, const char* what);
 int validate(const pond_config* c);
 int upload_table(pond_state* s);
 Layout layout_of(const pond_config* c);
+// The launches of one step of s, from buffer `in` to buffer 1 - in, on st
+// (no synchronisation, no allocation: safe under stream capture).
+int step_launches(pond_state* s, int in, hipStream_t st);
 
 }  // namespace pond
 

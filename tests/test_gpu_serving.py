@@ -39,14 +39,15 @@ def _alone(pond, wl, steps, transform=0):
     return [a.reshape(-1) for a in m]
 
 
-def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0, transforms=None, lattices=None):
+def _serve(pond, jobs, arena_bytes, max_active=64, timeout=120.0, transforms=None, lattices=None,
+           precisions=None):
     import torch
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     srv = pond.pond_server_create(arena.data_ptr(), arena_bytes, 0, max_active)
     ids = []
     try:
         for k, (wl, steps) in enumerate(jobs):
-            cfg = pond.make_config(wl, precision=pond.POND_MIXED,
+            cfg = pond.make_config(wl, precision=precisions[k] if precisions else pond.POND_MIXED,
                                    transform=transforms[k] if transforms else 0,
                                    lattice=lattices[k] if lattices else None)
             ids.append(pond.pond_submit(srv, cfg, *wl.fields(), steps, tag=k))
@@ -269,3 +270,31 @@ def test_d2q25_solves_are_served(pond):
             s.close()
             for a, b in zip(m, alone):
                 assert np.array_equal(a, b), k
+
+
+def test_fp64_and_1d_solves_are_served(pond):
+    """FP64 solves (2D D2Q16, D2Q9 and walled, D2Q25) and 1D solves (both
+    precisions) run their own step launches inside the served chunk graphs,
+    beside mixed 2D solves in the batched step: each result equals the same
+    solve alone, bit for bit."""
+    FP64, MIXED = pond.POND_FP64, pond.POND_MIXED
+    vort = inputs.vortex_2d(36, steps=1, mach=1.0, noise=1e-3, seed=41, ny=40)
+    quad = inputs.quadrants_2d(40, steps=1, seed=3, ny=36)
+    couette = inputs.thermal_couette_2d(32, nx=16, steps=1)
+    sod = inputs.sod_1d(200, steps=1)
+    jobs = [(vort, 21), (quad, 18), (sod, 40), (couette, 25), (sod, 33), (vort, 16), (quad, 12)]
+    precisions = [FP64, MIXED, MIXED, FP64, FP64, FP64, FP64]
+    lattices = [pond.POND_D2Q16, pond.POND_D2Q16, None, pond.POND_D2Q16, None, pond.POND_D2Q9,
+                pond.POND_D2Q25]
+    transforms = [0, 1, 0, 1, 0, 1, 1]
+    got = _serve(pond, jobs, 1 << 28, transforms=transforms, lattices=lattices,
+                 precisions=precisions)
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, _ = got[k]
+        assert rc == pond.POND_OK, k
+        s = pond.Solver(wl, precision=precisions[k], transform=transforms[k], lattice=lattices[k])
+        s.step(steps)
+        alone = [a.reshape(-1) for a in s.moments()]
+        s.close()
+        for a, b in zip(m, alone):
+            assert np.array_equal(a, b), k
