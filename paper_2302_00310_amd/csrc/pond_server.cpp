@@ -1,13 +1,15 @@
-// Serving loop of libpond.so: continuous batching of independent 2D solves.
+// Serving loop of libpond.so: continuous batching of independent solves.
 //
 // A server thread owns a device arena and a stream.  Requests are queued by
 // pond_submit (host copies of their inputs, no GPU work) and admitted first
 // come, first served as soon as their footprint fits a first-fit free list
 // over the arena and a batch slot is free.  Every iteration advances all
-// resident solves together by K steps: one batched step kernel per step
-// covers the tiles of all of them (a device table maps blocks to solves), and
-// the K launches are captured once per change of the resident set into a
-// HIP graph that is replayed while the set is unchanged.  Solves that reach
+// resident solves together by K steps: per step, one batched step kernel per
+// solve kind covers the tiles of the mixed-precision 2D solves (a device
+// table maps blocks to solves), after each multiscale solve's switch and each
+// walled solve's ghost layers; FP64, 1D and D2Q25 solves add their own step
+// launches.  The K steps are captured once per change of the resident set
+// into a HIP graph that is replayed while the set is unchanged.  Solves that reach
 // their step count are retired: moments copied to host, status recorded
 // (a non-physical state fails that solve only), arena released.
 #include <hip/hip_runtime.h>
