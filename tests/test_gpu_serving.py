@@ -298,3 +298,26 @@ def test_fp64_and_1d_solves_are_served(pond):
         s.close()
         for a, b in zip(m, alone):
             assert np.array_equal(a, b), k
+
+
+def test_zero_step_requests_return_their_initial_state(pond):
+    """nsteps = 0 for every solve kind: the result equals the moments of the
+    same solve created and never stepped, bit for bit."""
+    FP64, MIXED = pond.POND_FP64, pond.POND_MIXED
+    vort = inputs.vortex_2d(24, steps=1, mach=1.0, noise=1e-3, seed=42, ny=20)
+    sod = inputs.sod_1d(64, steps=1)
+    jobs = [(vort, 0), (sod, 0), (vort, 0), (vort, 0), (vort, 5)]
+    precisions = [FP64, MIXED, MIXED, MIXED, MIXED]
+    lattices = [pond.POND_D2Q16, None, pond.POND_D2Q25, pond.POND_D2Q9_D2Q16, pond.POND_D2Q16]
+    transforms = [0, 0, 1, 1, 0]
+    got = _serve(pond, jobs, 1 << 26, transforms=transforms, lattices=lattices,
+                 precisions=precisions)
+    for k, (wl, steps) in enumerate(jobs):
+        rc, m, _ = got[k]
+        assert rc == pond.POND_OK, k
+        s = pond.Solver(wl, precision=precisions[k], transform=transforms[k], lattice=lattices[k])
+        s.step(steps)
+        alone = [a.reshape(-1) for a in s.moments()]
+        s.close()
+        for a, b in zip(m, alone):
+            assert np.array_equal(a, b), k
