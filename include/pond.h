@@ -61,8 +61,7 @@ enum { POND_D1Q4 = 1, POND_D2Q16 = 2, POND_D2Q9 = 3, POND_D2Q9_D2Q16 = 4, POND_D
    (Sec. III B, full invariant moment system): needs POND_TF_GRAD and dim 2;
    no walls or body force.  Runs as four plain kernel launches per step
    (cell pass, x- and y-face passes, update) with the face data in the
-   arena (not fused like D2Q16); pond_export_state does not cover it
-   (POND_ERR_UNSUPPORTED). */
+   arena (not fused like D2Q16). */
 /* POND_D2Q9: the second-order f-lattice everywhere.  POND_D2Q9_D2Q16: the
    multiscale deployment (Sec. III C, Sec. IV C) -- each step, D2Q16 within
    two cells of a cell whose gradient indicator
@@ -165,7 +164,7 @@ int pond_totals_fixed(pond_state* s, int64_t out[8], int* scale_bits);
 /* Waits for the stream and writes the populations f~ (Qf planes of nx*ny
    doubles, i = i_x + q i_y, nodes ascending), g~ (Qg planes) and the frame
    (u_x, u_y, T planes) they are written in.  Any pointer may be NULL.
-   POND_ERR_UNSUPPORTED for POND_D2Q25 solves. */
+   Qf = 25 for POND_D2Q25 solves (i = i_x + 5 i_y). */
 int pond_export_state(pond_state* s, double* f, double* g, double* frame);
 
 /* Per cell (row-major [ny][nx], host arrays, either may be NULL): the

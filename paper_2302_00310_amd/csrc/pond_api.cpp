@@ -510,9 +510,66 @@ int pond_totals(pond_state* s, double out[4]) {
   return rc;
 }
 
+// D2Q25 export on the host: the stored planes hold f~ - rho W (25 tensor
+// weights of the D1Q5 rule) and g~ - (C_v - D/2) T rho W^g, as the fused
+// lattices store them; the frame comes from the ledger (eqs.
+// ConservationLaws, E), and the equilibria are added back in FP64.
+static int export_q25(pond_state* s, double* f, double* g, double* frame) {
+  int rc = sync_flag(s);
+  const size_t n = s->L.cells, chunk = std::min(n, size_t(1) << 18);
+  const size_t es = s->L.fp64 ? sizeof(double) : sizeof(float);
+  const int QF = s->L.QF, QG = s->L.QG, NP = s->L.NP;
+  const double w5[5] = {kW5B, kW5A, 8.0 / 15.0, kW5A, kW5B};
+  const double w3[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+  std::vector<unsigned char> raw(size_t(NP) * chunk * es);
+  std::vector<long long> led(4 * chunk);
+  const unsigned char* dn = static_cast<const unsigned char*>(s->n[s->cur]);
+  for (size_t first = 0; first < n; first += chunk) {
+    const size_t cnt = std::min(chunk, n - first);
+    for (int p = 0; p < NP; ++p)
+      POND_HIP(hipMemcpyAsync(raw.data() + size_t(p) * chunk * es, dn + (size_t(p) * n + first) * es,
+                              cnt * es, hipMemcpyDeviceToHost, s->stream));
+    for (int q = 0; q < 4; ++q)
+      POND_HIP(hipMemcpyAsync(led.data() + size_t(q) * chunk, s->U[s->cur] + size_t(q) * n + first,
+                              cnt * sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    POND_HIP(hipStreamSynchronize(s->stream));
+    auto stored = [&](int p, size_t k) {
+      const unsigned char* at = raw.data() + (size_t(p) * chunk + k) * es;
+      if (s->L.fp64) {
+        double v;
+        std::memcpy(&v, at, sizeof v);
+        return v;
+      }
+      float v;
+      std::memcpy(&v, at, sizeof v);
+      return double(v);
+    };
+    const double inv = s->args.inv_scale;
+    for (size_t k = 0; k < cnt; ++k) {
+      const size_t c = first + k;
+      const double rho = double(led[k]) * inv;
+      const double mx = double(led[chunk + k]) * inv, my = double(led[2 * chunk + k]) * inv;
+      const double e = double(led[3 * chunk + k]) * inv;
+      const double ux = mx / rho, uy = my / rho;
+      const double T = (e - 0.5 * (mx * ux + my * uy)) / rho * s->args.icv;
+      if (f)
+        for (int i = 0; i < QF; ++i) f[size_t(i) * n + c] = rho * (w5[i % 5] * w5[i / 5]) + stored(i, k);
+      if (g)
+        for (int i = 0; i < QG; ++i)
+          g[size_t(i) * n + c] = s->args.geq * T * rho * (w3[i % 3] * w3[i / 3]) + stored(QF + i, k);
+      if (frame) {
+        frame[c] = ux;
+        frame[n + c] = uy;
+        frame[2 * n + c] = T;
+      }
+    }
+  }
+  return rc;
+}
+
 int pond_export_state(pond_state* s, double* f, double* g, double* frame) {
   if (!s || !s->initialized) return fail(POND_ERR_INVALID, "fields not initialised");
-  if (s->L.q25) return fail(POND_ERR_UNSUPPORTED, "export covers the D2Q16 and D2Q9 f-lattices");
+  if (s->L.q25) return export_q25(s, f, g, frame);
   int rc = sync_flag(s);
   const size_t n = s->L.cells, chunk = s->L.stage_cells, rows = size_t(s->L.NP + 3);
   const int QF = s->L.QF, QG = s->L.QG;

@@ -252,7 +252,7 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = pond_create(self.cfg, self.arena.data_ptr(), self.bytes, self.stream.cuda_stream)
         self.n = wl.nx * wl.ny
-        self.qf, self.qg = (4, 3) if wl.dim == 1 else (16, 9)
+        self.qf, self.qg = (4, 3) if wl.dim == 1 else (25 if self.cfg.lattice == POND_D2Q25 else 16, 9)
         if init:
             pond_init_fields(self.h, *wl.fields())
 

@@ -151,3 +151,26 @@ def test_d2q25_checkpoint_resume_bitwise(pond, tmp_path):
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(FP64, 1e-12), (MIXED, 1e-5)])
+def test_d2q25_export_matches_oracle_state(pond, precision, tol):
+    """pond_export_state on D2Q25: the 25 f and 9 g populations in the cell
+    frames and the frames themselves equal the oracle's state (scale-relative
+    max error; FP32 storage of the non-equilibrium parts in mixed)."""
+    wl = CASES["quadrants_35x31"]()
+    s = pond.Solver(wl, precision=precision, transform=GRAD, lattice=Q25)
+    o = oracle.Oracle(wl, transform=GRAD, flat=O_Q25)
+    try:
+        f, g, fr = s.export_state()
+        fo, go, fro = o.get_state()
+        assert f.shape == fo.shape == (25, wl.ny, wl.nx) and g.shape == go.shape
+        s.step(12)
+        o.step(12)
+        f, g, fr = s.export_state()
+        fo, go, fro = o.get_state()
+        for a, b in ((f, fo), (g, go), (fr, fro)):
+            err = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+            assert err <= tol, err
+    finally:
+        s.close()
